@@ -1,0 +1,114 @@
+"""Top-k and k-selection by definition (oracle; test infrastructure only).
+
+Problem statement (Section 1): top-k returns the k largest elements of V,
+k-selection the k-th largest.  This project fixes what the paper leaves open:
+
+* order: ``rank_key`` (uint32 as is; float32 by IEEE totalOrder);
+* ties: among equal keys the lower position ranks first, so position i
+  precedes j iff key[i] > key[j] or (key[i] == key[j] and i < j);
+* output: the k first positions in that order, i.e. values sorted by key
+  descending with ties in ascending position; the k-th value counts
+  multiplicity (the value at output slot k-1).
+
+Every function returns ``(values, indices)`` with ``values`` the input's own
+bit patterns at ``indices``.
+"""
+from __future__ import annotations
+
+import heapq
+
+import numpy as np
+
+from .order import rank_key
+
+
+def _check(values: np.ndarray, k: int) -> int:
+    n = int(np.asarray(values).shape[0])
+    if not (1 <= k <= n):
+        raise ValueError(f"need 1 <= k <= n, got k={k}, n={n}")
+    return n
+
+
+def topk_bruteforce(values: np.ndarray, k: int, dtype: str):
+    """O(n^2) ranks straight from the definition (pure Python; n <= a few thousand).
+
+    rank(i) = #{j : key[j] > key[i]} + #{j < i : key[j] == key[i]}; the output
+    slot r holds the unique i with rank(i) == r.
+    """
+    n = _check(values, k)
+    key = [int(x) for x in rank_key(values, dtype)]
+    out = [None] * n
+    for i in range(n):
+        r = 0
+        for j in range(n):
+            if key[j] > key[i] or (key[j] == key[i] and j < i):
+                r += 1
+        out[r] = i
+    idx = np.array(out[:k], dtype=np.int64)
+    return np.asarray(values)[idx], idx
+
+
+def topk_sort(values: np.ndarray, k: int, dtype: str):
+    """Sort-and-choose (Section 2.2): sort every position by (key desc, index asc), keep k."""
+    n = _check(values, k)
+    key = rank_key(values, dtype)
+    order = np.lexsort((np.arange(n, dtype=np.int64), -key))
+    idx = order[:k].astype(np.int64)
+    return np.asarray(values)[idx], idx
+
+
+def topk_select(values: np.ndarray, k: int, dtype: str):
+    """k-selection first, then extraction (the selection route the paper's
+    top-k algorithms follow, Section 2.2):
+
+    1. T = the k-th largest key (numpy introselect on the rank keys);
+    2. g = #{key > T};
+    3. take every position with key > T, and the k - g lowest positions with
+       key == T, in one ascending pass;
+    4. order those k by (key desc, index asc).
+    """
+    n = _check(values, k)
+    key = rank_key(values, dtype)
+    T = np.partition(key, n - k)[n - k]
+    above = np.flatnonzero(key > T)
+    g = above.shape[0]
+    ties = np.flatnonzero(key == T)[: k - g]
+    idx = np.concatenate([above, ties]).astype(np.int64)
+    order = np.lexsort((idx, -key[idx]))
+    idx = idx[order]
+    return np.asarray(values)[idx], idx
+
+
+def topk_heap(values: np.ndarray, k: int, dtype: str):
+    """The textbook priority-queue top-k (Section 1): a size-k min-heap slides
+    over V; an element replaces the heap minimum when it ranks higher.
+
+    Heap items are (key, -index) so the heap root is the lowest-ranked kept
+    element (smallest key; among equal keys, the largest index).  Pure Python.
+    """
+    n = _check(values, k)
+    key = [int(x) for x in rank_key(values, dtype)]
+    heap = []
+    for i in range(n):
+        item = (key[i], -i)
+        if len(heap) < k:
+            heapq.heappush(heap, item)
+        elif item > heap[0]:
+            heapq.heapreplace(heap, item)
+    kept = sorted(heap, reverse=True)
+    idx = np.array([-m for _, m in kept], dtype=np.int64)
+    return np.asarray(values)[idx], idx
+
+
+def topk(values: np.ndarray, k: int, dtype: str):
+    """Reference answer at any size: the selection route (fast, numpy)."""
+    return topk_select(values, k, dtype)
+
+
+def kth_value(values: np.ndarray, k: int, dtype: str):
+    """k-selection (Section 1): the k-th largest value, counting multiplicity."""
+    n = _check(values, k)
+    key = rank_key(values, dtype)
+    T = np.partition(key, n - k)[n - k]
+    i = int(np.flatnonzero(key == T)[0])
+    return np.asarray(values)[i]

@@ -1,0 +1,65 @@
+"""The oracle against facts outside itself: brute force, closed forms,
+library routines, IEEE totalOrder and the paper's worked example."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stages
+import oracle_pins as pins
+
+ROUTES = [oracle.topk_sort, oracle.topk_select, oracle.topk_heap]
+
+
+@pytest.mark.parametrize("fn", ROUTES + [oracle.topk_bruteforce], ids=lambda f: f.__name__)
+def test_exhaustive_tiny(fn):
+    pins.pin_exhaustive_u32(fn, max_len=5 if fn is not oracle.topk_bruteforce else 4)
+
+
+@pytest.mark.parametrize("fn", ROUTES, ids=lambda f: f.__name__)
+def test_closed_forms(fn):
+    pins.pin_closed_forms_u32(fn)
+
+
+@pytest.mark.parametrize("fn", ROUTES + [oracle.topk_bruteforce], ids=lambda f: f.__name__)
+def test_float_total_order(fn):
+    pins.pin_float_order(fn)
+
+
+def test_kth():
+    pins.pin_kth(oracle.kth_value)
+
+
+@pytest.mark.parametrize("dtype", ["u32", "f32"])
+def test_routes_agree_random(dtype):
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 63, 64, 65, 1000, 4097):
+        if dtype == "u32":
+            v = rng.integers(0, 2 ** 32, size=n, dtype=np.uint32)
+            v[rng.integers(0, n, size=n // 4)] = v[0]  # plant ties
+        else:
+            v = rng.standard_normal(n).astype(np.float32)
+            v[rng.integers(0, n, size=n // 4)] = v[0]
+        for k in sorted({1, n, max(1, n // 2), min(n, 17)}):
+            a = oracle.topk_sort(v, k, dtype)[1]
+            b = oracle.topk_select(v, k, dtype)[1]
+            assert (a == b).all()
+            if n <= 1000:
+                c = oracle.topk_heap(v, k, dtype)[1]
+                assert (a == c).all()
+
+
+def test_argument_errors():
+    v = np.zeros(4, dtype=np.uint32)
+    for k in (0, 5):
+        with pytest.raises(ValueError):
+            oracle.topk_select(v, k, "u32")
+    with pytest.raises(TypeError):
+        oracle.topk_select(v.astype(np.int32), 1, "u32")
+
+
+def test_delegates_bruteforce():
+    pins.pin_delegates_bruteforce(stages.delegates)
+
+
+def test_paper_worked_example():
+    pins.pin_paper_example(stages)

@@ -1,0 +1,171 @@
+"""Planted mistakes in copies of the oracle must trip at least one pin.
+
+Each mutant is a plausible slip (a wrong sign, a dropped term, an off-by-one,
+a reversed tie rule, a transposed operand).  The mutants live here, on the
+CPU; the oracle itself is never modified.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import order, stages, topk as T
+import oracle_pins as pins
+
+
+def _key_float_value(values, dtype):
+    # mistake: compare floats by value (loses -0 < +0 and the NaN places)
+    if dtype == "f32":
+        return np.asarray(values).astype(np.float64)
+    return order.rank_key(values, dtype)
+
+
+def _key_no_flip(values, dtype):
+    # mistake: signed view without reflecting negative magnitudes
+    if dtype == "f32":
+        return np.asarray(values).view(np.int32).astype(np.int64)
+    return order.rank_key(values, dtype)
+
+
+def _sort_ties_desc(values, k, dtype):
+    # mistake: ties in descending position
+    n = values.shape[0]
+    key = order.rank_key(values, dtype)
+    o = np.lexsort((-np.arange(n), -key))[:k]
+    return values[o], o
+
+
+def _select_off_by_one(values, k, dtype):
+    # mistake: partition index n-k+1 instead of n-k
+    n = values.shape[0]
+    key = order.rank_key(values, dtype)
+    T_ = np.partition(key, min(n - 1, n - k + 1))[min(n - 1, n - k + 1)]
+    above = np.flatnonzero(key > T_)
+    ties = np.flatnonzero(key == T_)[: max(0, k - above.shape[0])]
+    idx = np.concatenate([above, ties])
+    o = np.lexsort((idx, -key[idx]))
+    return values[idx[o]], idx[o]
+
+
+def _heap_wrong_tiebreak(values, k, dtype):
+    # mistake: heap items (key, index) instead of (key, -index)
+    import heapq
+    key = [int(x) for x in order.rank_key(values, dtype)]
+    h = []
+    for i in range(len(key)):
+        it = (key[i], i)
+        if len(h) < k:
+            heapq.heappush(h, it)
+        elif it > h[0]:
+            heapq.heapreplace(h, it)
+    idx = np.array([i for _, i in sorted(h, reverse=True)])
+    return values[idx], idx
+
+
+def _with_key(fn_key):
+    def f(values, k, dtype):
+        n = values.shape[0]
+        key = fn_key(values, dtype)
+        o = np.lexsort((np.arange(n), -key))[:k]
+        return values[o], o
+    return f
+
+
+MUTANTS = {
+    "float_by_value": (_with_key(_key_float_value), pins.pin_float_order),
+    "no_negative_flip": (_with_key(_key_no_flip), pins.pin_float_order),
+    "ties_descending": (_sort_ties_desc, pins.pin_closed_forms_u32),
+    "select_off_by_one": (_select_off_by_one, pins.pin_exhaustive_u32),
+    "heap_tiebreak": (_heap_wrong_tiebreak, pins.pin_exhaustive_u32),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_definition_mutant_caught(name):
+    fn, pin = MUTANTS[name]
+    with pytest.raises(AssertionError):
+        pin(fn)
+
+
+def test_real_oracle_passes_same_pins():
+    for fn, pin in MUTANTS.values():
+        pin(oracle.topk_sort)
+
+
+class _StagesMutant:
+    """stages module with one function swapped for a broken one."""
+
+    def __init__(self, **over):
+        self.__dict__.update({k: getattr(stages, k) for k in
+                              ("delegates", "first_topk", "qualifying", "concatenate",
+                               "alpha_rule", "at_or_above")})
+        self.__dict__.update(over)
+
+    def method_topk(self, values, k, dtype, alpha, beta):
+        dkey, didx = self.delegates(values, dtype, alpha, beta)
+        taken, t = self.first_topk(dkey, didx, k)
+        qual = self.qualifying(taken, t)
+        cand = self.concatenate(values, dtype, alpha, dkey, didx, taken, qual, t)
+        sub = np.asarray(values)[cand]
+        _, j = oracle.topk_sort(sub, min(k, sub.shape[0]), dtype)
+        return np.asarray(values)[cand[j]], cand[j], {}
+
+
+def _delegates_last_max(values, dtype, alpha, beta):
+    # mistake: keep the last (not first) position among equal keys
+    key = order.rank_key(values, dtype)
+    n = key.shape[0]
+    L = 1 << alpha
+    S = -(-n // L)
+    dk = np.full((S, beta), stages.PAD_KEY, dtype=np.int64)
+    di = np.full((S, beta), order.INVALID_INDEX, dtype=np.int64)
+    for s in range(S):
+        pos = list(range(s * L, min(n, (s + 1) * L)))
+        best = sorted(pos, key=lambda i: (-key[i], -i))[:beta]
+        for j, i in enumerate(best):
+            dk[s, j], di[s, j] = key[i], i
+    return dk, di
+
+
+def _qualifying_any(taken, t):
+    # mistake: Rule 3 with "any" delegate taken instead of all of them
+    return taken.any(axis=1) if t is not None else np.ones(taken.shape[0], bool)
+
+
+def _concat_strict(values, dtype, alpha, dkey, didx, taken, qual, t):
+    # mistake: filter strictly above t (drops t itself)
+    key = order.rank_key(values, dtype)
+    n = key.shape[0]
+    L = 1 << alpha
+    parts = []
+    for s in np.flatnonzero(qual):
+        pos = np.arange(s * L, min(n, (s + 1) * L))
+        kk = key[pos]
+        parts.append(pos[(kk > t[0]) | ((kk == t[0]) & (pos < t[1]))])
+    parts.append(didx[taken & ~qual[:, None]].astype(np.int64))
+    return np.unique(np.concatenate(parts))
+
+
+def _alpha_ceil(n, k, const=3.0):
+    import math
+    return int(math.ceil(0.5 * (math.log2(n) - math.log2(k) + const)))
+
+
+def _first_topk_kplus1(dkey, didx, k):
+    # mistake: threshold taken at the (k+1)-th delegate
+    return stages.first_topk(dkey, didx, k + 1)
+
+
+@pytest.mark.parametrize("name,mut,pin", [
+    ("delegate_last_max", dict(delegates=_delegates_last_max), pins.pin_delegates_bruteforce),
+    ("qualify_any", dict(qualifying=_qualifying_any), pins.pin_paper_example),
+    ("filter_strict", dict(concatenate=_concat_strict), pins.pin_paper_example),
+    ("alpha_ceil", dict(alpha_rule=_alpha_ceil), pins.pin_paper_example),
+    ("threshold_k_plus_1", dict(first_topk=_first_topk_kplus1), pins.pin_paper_example),
+])
+def test_stage_mutant_caught(name, mut, pin):
+    m = _StagesMutant(**mut)
+    with pytest.raises(AssertionError):
+        if pin is pins.pin_delegates_bruteforce:
+            pin(m.delegates)
+        else:
+            pin(m)

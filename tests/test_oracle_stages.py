@@ -1,0 +1,75 @@
+"""The method-stage model: Rule 2's bound, Rule 3's exactness, equivalence of
+the literal and threshold forms of the subrange test, and agreement of the
+whole pipeline with the definition for every alpha / beta."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import stages
+
+
+def _inputs():
+    yield "uniform", *synth.keys("uniform_u32", 5000, 1)
+    yield "normal", *synth.keys("normal_f32", 5000, 2)
+    yield "sorted", *synth.keys("sorted_f32", 4096, 3)
+    yield "heavydup", *synth.keys("heavydup_u32", 5000, 4)
+    yield "tiny_alphabet", np.array([1, 0, 1, 1, 0, 2, 2, 0, 1] * 7, dtype=np.uint32), "u32"
+
+
+@pytest.mark.parametrize("name,v,dtype", list(_inputs()), ids=lambda x: x if isinstance(x, str) else None)
+def test_pipeline_matches_definition(name, v, dtype):
+    n = v.shape[0]
+    for alpha in (0, 1, 2, 4, 6, 9, 13):
+        for beta in (1, 2, 3, 4, 8):
+            for k in sorted({min(n, kk) for kk in (1, 2, 16, 100, n // 3, n)}):
+                vals, idx, info = stages.method_topk(v, k, dtype, alpha, beta)
+                _, want = oracle.topk_sort(v, k, dtype)
+                assert (idx == want).all(), (name, alpha, beta, k)
+                t = info["t"]
+                key = oracle.rank_key(v, dtype)
+                if t is not None:
+                    # Rule 2: the k-th delegate never ranks above the k-th element of V.
+                    kk, ki = int(key[want[-1]]), int(want[-1])
+                    assert (t[0] < kk) or (t[0] == kk and t[1] >= ki)
+                # the candidates contain the answer
+                assert np.isin(want, info["candidates"]).all()
+                # literal Rule 3 and the threshold form give the same candidates
+                if t is not None:
+                    scan = stages.scanned_threshold_form(info["dkey"], info["didx"], t)
+                    assert (scan <= info["qualifying"]).all()
+                    L = 1 << alpha
+                    taken = info["taken"]
+                    parts = [info["didx"][taken & ~scan[:, None]]]
+                    for s in np.flatnonzero(scan):
+                        pos = np.arange(s * L, min(n, (s + 1) * L))
+                        parts.append(pos[stages.at_or_above(key[pos], pos, t)])
+                    alt = np.unique(np.concatenate(parts).astype(np.int64))
+                    assert (alt == info["candidates"]).all()
+
+
+def test_scanned_subranges_bound():
+    """Each scanned subrange holds beta delegates ranked above t, and at most
+    k-1 delegates rank above t, so fewer than k/beta subranges are scanned."""
+    v, dtype = synth.keys("uniform_u32", 1 << 16, 9)
+    for alpha, beta, k in [(6, 1, 64), (6, 2, 64), (4, 4, 500), (8, 8, 1000)]:
+        dkey, didx = stages.delegates(v, dtype, alpha, beta)
+        taken, t = stages.first_topk(dkey, didx, k)
+        scan = stages.scanned_threshold_form(dkey, didx, t)
+        assert scan.sum() * beta <= k - 1
+
+
+def test_few_delegates_means_no_threshold():
+    v = synth.uniform_u32(100, 1)
+    dkey, didx = stages.delegates(v, "u32", 6, 1)  # 2 subranges
+    taken, t = stages.first_topk(dkey, didx, 50)
+    assert t is None
+    assert stages.qualifying(taken, t).all()
+
+
+def test_alpha_rule_monotone():
+    assert stages.alpha_rule(2 ** 30, 1) == 16
+    assert stages.alpha_rule(2 ** 30, 2 ** 10) == 11
+    assert stages.alpha_rule(2 ** 30, 2 ** 17) == 8
+    assert stages.alpha_rule(2 ** 20, 2 ** 20) == 1
+    assert stages.alpha_rule(16, 2 ** 20) == 0
