@@ -1,0 +1,156 @@
+/* drtopk -- delegate-centric top-k and k-selection on AMD MI355X (gfx950).
+ *
+ * Implements the method of "Dr. Top-k: Delegate-Centric Top-k on GPUs"
+ * (Gaihre et al., SC'21).  Problem statement (paper, Section 1): top-k returns
+ * the k largest elements of an input vector V; k-selection returns the k-th
+ * largest.  The method (Sections 4-5): cut V into subranges of 2^alpha
+ * elements, keep the top-beta of each as delegates (Rules 1 and 3), take the
+ * k-th largest delegate as a lower bound of the answer's k-th element (Rule 2),
+ * skip every subrange that cannot reach it, and select among the survivors.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - keys are uint32 (as the paper evaluates) or float32, the latter ordered
+ *     by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN);
+ *   - among equal keys the lower position ranks first, so the answer is unique:
+ *     out_vals is sorted by key descending, ties by ascending position, and
+ *     out_vals[k-1] is the k-th largest counting multiplicity;
+ *   - output values are the input's own bit patterns (NaN payloads and -0 kept).
+ *
+ * Memory: every key / output pointer is DEVICE memory owned by the caller.
+ * The library keeps one workspace per (device, stream) that grows on demand
+ * (freed by drtopk_release_workspace).  All calls are asynchronous on
+ * `stream` (a hipStream_t; NULL means the default stream); outputs are valid
+ * once the stream reaches that point.  Calls on different streams may run
+ * concurrently.  No C++ exception crosses this interface.
+ *
+ * Errors are returned synchronously: DRTOPK_EINVAL for bad arguments (null
+ * pointer, k == 0, k > n, n >= 2^32, unknown dtype), DRTOPK_ENOMEM when the
+ * workspace cannot be allocated (nothing is launched), DRTOPK_EDEVICE when a
+ * launch or device query fails.  Faults inside kernels surface at the next
+ * synchronisation as HIP errors.
+ */
+#ifndef DRTOPK_H
+#define DRTOPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { DRTOPK_U32 = 0, DRTOPK_F32 = 1 } drtopk_dtype_t;
+
+typedef enum {
+  DRTOPK_OK = 0,
+  DRTOPK_EINVAL = 1,
+  DRTOPK_ENOMEM = 2,
+  DRTOPK_EDEVICE = 3,
+  DRTOPK_EUNSUPPORTED = 4
+} drtopk_status_t;
+
+/* Top-k (paper, Section 1).
+ *   keys     device, n elements of `dtype` (4 bytes each); any alignment
+ *            (16-byte aligned input takes the 128-bit load path)
+ *   n        1 <= n < 2^32
+ *   k        1 <= k <= n
+ *   out_vals device, k elements of `dtype`: the k largest, sorted as above
+ *   out_idx  device, k uint32 positions into keys (out_vals[r] == keys[out_idx[r]]),
+ *            or NULL
+ *   stream   hipStream_t or NULL */
+int topk_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals,
+                uint32_t* out_idx, void* stream);
+
+/* k-selection (paper, Section 1): writes the k-th largest value (1 element of
+ * `dtype`, device memory) to out_kth.  Same argument rules as topk_select. */
+int kth_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_kth, void* stream);
+
+/* One problem of a batch.  All pointers are device memory; out_vals/out_idx
+ * hold k elements, out_kth one element; out_idx and out_kth may be NULL. */
+typedef struct {
+  const void* keys;
+  uint64_t n;
+  uint32_t k;
+  uint32_t dtype;
+  void* out_vals;
+  uint32_t* out_idx;
+  void* out_kth;
+} drtopk_problem_t;
+
+/* Many independent top-k problems (the paper's Section 1 problem, applied to
+ * each).  `problems` is a HOST array of `count` descriptors, copied during the
+ * call.  Results equal topk_select on each problem alone, bit for bit. */
+int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream);
+
+/* Explicit method parameters (for tests, tuning and ablations).
+ *   alpha  subrange = 2^alpha elements (Section 5.1); -1 = planner's choice
+ *   beta   delegates per subrange (Rule 3): 1, 2, 4 or 8; 0 = planner's choice
+ *   mode   0 = planner's choice, 1 = delegate method, 2 = plain radix select
+ *          over V with no delegates */
+typedef struct {
+  int32_t alpha;
+  int32_t beta;
+  int32_t mode;
+  int32_t reserved;
+} drtopk_options_t;
+
+/* Counters of one call (host struct, filled after the call's work finishes;
+ * passing non-NULL makes the call synchronise `stream`). */
+typedef struct {
+  int32_t mode;          /* 1 delegate method, 2 plain radix select */
+  int32_t alpha, beta;
+  uint64_t subranges;    /* S = ceil(n / 2^alpha) */
+  uint64_t delegates;    /* |D| = S * beta */
+  uint64_t scanned;      /* subranges re-read after the threshold */
+  uint64_t candidates;   /* survivors handed to the second select */
+  uint32_t t_key_bits;   /* the k-th delegate (Rule 2), input bit pattern */
+  uint32_t t_idx;        /* its position */
+} drtopk_stats_t;
+
+/* topk_select with explicit options (NULL = defaults) and optional stats. */
+int topk_select_ex(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals,
+                   uint32_t* out_idx, const drtopk_options_t* opt, drtopk_stats_t* stats,
+                   void* stream);
+
+/* The delegate vector alone (Rules 1 and 3) for stage-by-stage checks:
+ * writes S * beta entries, S = ceil(n / 2^alpha): out_dkeys[s*beta + j] is the
+ * j-th delegate's value (input bit pattern) and out_didx[s*beta + j] its
+ * position, rows ordered by key descending then position ascending; a
+ * subrange with fewer than beta elements pads with position 0xFFFFFFFF.
+ * alpha in [0, 24], beta in {1, 2, 4, 8}; device buffers. */
+int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int beta,
+                     void* out_dkeys, uint32_t* out_didx, void* stream);
+
+/* The survivors of the filter for given alpha/beta (Rules 1-3): writes their
+ * positions (unordered) to out_pos (device, capacity `cap` entries) and their
+ * count to *count (host; synchronises `stream`).  DRTOPK_EINVAL if cap is too
+ * small for the count. */
+int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta,
+                      uint32_t* out_pos, uint64_t cap, uint64_t* count, void* stream);
+
+/* The planner's choice for a problem (no device work). */
+int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out);
+
+/* Phase timing with HIP events, for measurement runs.  While enabled, every
+ * top-k call records events on its own stream around the delegate pass (the
+ * one pass that streams all of V) and around everything after it.
+ * drtopk_timing_read synchronises on those events, returns the summed
+ * milliseconds of each phase and the number of calls since the last read,
+ * and resets the counters.  Enabling costs two event pairs per call. */
+int drtopk_timing_enable(int on);
+int drtopk_timing_read(double* delegate_ms, double* tail_ms, uint64_t* calls);
+
+/* Frees the calling thread's current device's workspaces (synchronises it). */
+int drtopk_release_workspace(void);
+
+/* Human-readable name of a status code (static string). */
+const char* drtopk_status_string(int status);
+
+/* Library version string. */
+const char* drtopk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRTOPK_H */

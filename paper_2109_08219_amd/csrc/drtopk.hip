@@ -1,0 +1,620 @@
+// Host side of drtopk: planner, per-stream workspace, kernel sequence, C-ABI.
+//
+// One call enqueues, on the caller's stream and with no host synchronisation:
+//   k_init -> delegate pass (+ first digit of the delegate select) -> five more
+//   digit passes over the delegates (threshold t, Rule 2) -> qualify (Rule 3)
+//   -> scan of the qualifying subranges -> survivor select -> sorted output.
+// Small survivor counts finish in one LDS-resident workgroup; large ones take
+// the multi-workgroup radix select, an exact compaction and a merge sort.  The
+// host cannot see the survivor count, so both routes are enqueued and each
+// kernel checks a device-side gate and returns at once when not needed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "drtopk.h"
+#include "kernels.h"
+
+namespace drtopk {
+namespace {
+
+constexpr double kAlphaConst = 3.0;  // Rule 4's const; the paper tuned it to 3
+
+struct Plan {
+  int mode = 0;  // 1 delegate method, 2 plain radix select on V
+  int alpha = 0, beta = 1;
+  int dt = 0;
+  uint64_t n = 0;
+  uint32_t k = 0;
+  uint64_t S = 0, nd = 0, cap_c = 0, chunk = 0, M = 0;
+  uint32_t kD = 0;   // rank sought among the delegates: min(k, |D|)
+  bool all = false;  // fewer real delegates than k: no threshold, every subrange qualifies
+  bool vec = false;
+  size_t off_ctl = 0, off_dkey = 0, off_didx = 0, off_q = 0, off_ckey = 0, off_cidx = 0;
+  size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, total = 0;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int rule_alpha(uint64_t n, uint32_t k) {
+  const double a = 0.5 * (std::log2((double)n) - std::log2((double)k) + kAlphaConst);
+  int al = (int)std::floor(a);
+  if (al < 2) al = 2;
+  if (al > 24) al = 24;
+  return al;
+}
+
+int default_beta(uint64_t n, uint32_t k) {
+  (void)n;
+  return k <= 4096 ? 1 : 2;
+}
+
+bool valid_beta(int b) { return b == 1 || b == 2 || b == 4 || b == 8; }
+
+int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P) {
+  Plan p;
+  p.n = n;
+  p.k = k;
+  p.dt = dt;
+  p.vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
+  int mode = opt ? opt->mode : 0;
+  if (mode < 0 || mode > 2) return DRTOPK_EINVAL;
+  if (mode == 0) mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
+  p.mode = mode;
+  if (mode == 1) {
+    p.beta = (opt && opt->beta > 0) ? opt->beta : default_beta(n, k);
+    if (!valid_beta(p.beta)) return DRTOPK_EINVAL;
+    p.alpha = (opt && opt->alpha >= 0) ? opt->alpha : rule_alpha(n, k);
+    if (p.alpha > 24) return DRTOPK_EINVAL;
+    const uint64_t L = 1ull << p.alpha;
+    p.S = (n + L - 1) >> p.alpha;
+    p.nd = p.S * (uint64_t)p.beta;
+    const uint64_t full = n >> p.alpha, last = n & (L - 1);
+    const uint64_t per_full = L < (uint64_t)p.beta ? L : (uint64_t)p.beta;
+    const uint64_t nd_valid = full * per_full + (last < (uint64_t)p.beta ? last : (uint64_t)p.beta);
+    p.kD = p.nd < (uint64_t)k ? (uint32_t)p.nd : k;
+    if (nd_valid < k) {
+      p.cap_c = n;
+      p.all = true;
+    } else {
+      const uint64_t c = (uint64_t)((k - 1) / p.beta) * L + k;
+      p.cap_c = c < n ? c : n;
+    }
+    p.chunk = (1ull << 18) > 4 * L ? (1ull << 18) : 4 * L;
+  }
+  if (k > (uint32_t)kSmallCap) {
+    uint64_t tiles = ((uint64_t)k + kSortTile - 1) / kSortTile, t2 = 1;
+    while (t2 < tiles) t2 <<= 1;
+    p.M = t2 * kSortTile;
+  }
+  size_t off = 0;
+  auto seg = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  p.off_ctl = seg(sizeof(Ctl));
+  if (mode == 1) {
+    p.off_dkey = seg(p.nd * 4);
+    p.off_didx = seg(p.nd * 4);
+    p.off_q = seg(p.S * 4);
+    p.off_ckey = seg(p.cap_c * 4);
+    p.off_cidx = seg(p.cap_c * 4);
+  }
+  p.off_okey = seg((size_t)k * 4);
+  p.off_oidx = seg((size_t)k * 4);
+  if (p.M) {
+    p.off_A = seg(p.M * 8);
+    p.off_B = seg(p.M * 8);
+  }
+  p.total = off;
+  *P = p;
+  return DRTOPK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace: one per (device, stream); a call holds its entry's lock while it
+// enqueues, so sequences on one stream never interleave.
+struct Workspace {
+  std::mutex mu;
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, void*>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace* workspace_entry(int dev, void* stream) {
+  std::lock_guard<std::mutex> g(g_mu);
+  auto& slot = g_ws[{dev, stream}];
+  if (!slot) slot.reset(new (std::nothrow) Workspace());
+  return slot.get();
+}
+
+// Called with ws->mu held.
+int ensure_bytes(Workspace* ws, size_t need) {
+  if (ws->bytes >= need) return DRTOPK_OK;
+  if (ws->ptr) {
+    if (hipFree(ws->ptr) != hipSuccess) return DRTOPK_EDEVICE;
+    ws->ptr = nullptr;
+    ws->bytes = 0;
+  }
+  size_t want = need + need / 8;  // headroom to avoid regrowing on small changes
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    if (hipMalloc(&p, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return DRTOPK_ENOMEM;
+    }
+    want = need;
+  }
+  ws->ptr = p;
+  ws->bytes = want;
+  return DRTOPK_OK;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// optional phase timing (events on the call's own stream)
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  struct Rec { hipEvent_t a, b, c; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+} g_timing;
+
+struct PhaseMarks {
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr;
+  bool on = false;
+  void begin(hipStream_t st) {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    if (!g_timing.on) return;
+    a = g_timing.take(); b = g_timing.take(); c = g_timing.take();
+    on = a && b && c;
+    (void)st;
+  }
+  void start(hipStream_t st) { if (on) (void)hipEventRecord(a, st); }
+  void mid(hipStream_t st) { if (on) (void)hipEventRecord(b, st); }
+  void end(hipStream_t st) {
+    if (!on) return;
+    (void)hipEventRecord(c, st);
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    g_timing.pending.push_back({a, b, c});
+  }
+};
+
+// ---------------------------------------------------------------------------
+// kernel sequence
+template <int DT>
+struct Runner {
+  static void delegate(const Plan& p, const uint32_t* keys, uint32_t* dkey, uint32_t* didx, Ctl* ctl,
+                       hipStream_t st) {
+    if (p.alpha >= 2) {
+      const unsigned g = (unsigned)((p.n + p.chunk - 1) / p.chunk);
+#define DRTOPK_DEL(B, V) \
+  hipLaunchKernelGGL((k_delegate<DT, B, V>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.chunk, dkey, didx, ctl, p.kD)
+      switch (p.beta * 2 + (p.vec ? 1 : 0)) {
+        case 2: DRTOPK_DEL(1, false); break;
+        case 3: DRTOPK_DEL(1, true); break;
+        case 4: DRTOPK_DEL(2, false); break;
+        case 5: DRTOPK_DEL(2, true); break;
+        case 8: DRTOPK_DEL(4, false); break;
+        case 9: DRTOPK_DEL(4, true); break;
+        case 16: DRTOPK_DEL(8, false); break;
+        default: DRTOPK_DEL(8, true); break;
+      }
+#undef DRTOPK_DEL
+    } else {
+      const unsigned g = grid_for(p.S, 256, 4096);
+#define DRTOPK_DELT(B) \
+  hipLaunchKernelGGL((k_delegate_thread<DT, B>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.S, dkey, didx, ctl, p.kD)
+      switch (p.beta) {
+        case 1: DRTOPK_DELT(1); break;
+        case 2: DRTOPK_DELT(2); break;
+        case 4: DRTOPK_DELT(4); break;
+        default: DRTOPK_DELT(8); break;
+      }
+#undef DRTOPK_DELT
+    }
+  }
+
+  static void qualify(const Plan& p, uint32_t* dkey, uint32_t* didx, Ctl* ctl, uint32_t* Q, uint32_t* ckey,
+                      uint32_t* cidx, hipStream_t st) {
+    const unsigned g = grid_for(p.S, 256, 8192);
+    switch (p.beta) {
+      case 1: hipLaunchKernelGGL((k_qualify<1>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
+      case 2: hipLaunchKernelGGL((k_qualify<2>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
+      case 4: hipLaunchKernelGGL((k_qualify<4>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
+      default: hipLaunchKernelGGL((k_qualify<8>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
+    }
+  }
+
+  // The k sorted outputs from okey/oidx (exactly k entries), k > kSmallCap.
+  static void big_sort(const Plan& p, void* ws, uint32_t* out_vals, uint32_t* out_idx, uint32_t* out_kth,
+                       hipStream_t st) {
+    uint64_t* A = at<uint64_t>(ws, p.off_A);
+    uint64_t* B = at<uint64_t>(ws, p.off_B);
+    hipLaunchKernelGGL(k_blocksort, dim3((unsigned)(p.M / kSortTile)), dim3(1024), 0, st,
+                       at<uint32_t>(ws, p.off_okey), at<uint32_t>(ws, p.off_oidx), p.k, A);
+    for (uint64_t run = kSortTile; run < p.M; run <<= 1) {
+      const int last = (2 * run == p.M) ? 1 : 0;
+      hipLaunchKernelGGL((k_merge<DT>), dim3((unsigned)(p.M / 256)), dim3(256), 0, st, A, B, p.M, run, last, p.k,
+                         out_vals, out_idx, out_kth);
+      std::swap(A, B);
+    }
+  }
+
+  // filter_only: stop once the survivors are known (stage checks).
+  static void run(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
+                  uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st) {
+    PhaseMarks pm;
+    pm.begin(st);
+    run_inner(p, keys, ws, out_vals, out_idx, out_kth, kth_only, filter_only, st, pm);
+    pm.end(st);
+  }
+
+  static void run_inner(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
+                        uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st, PhaseMarks& pm) {
+    Ctl* ctl = at<Ctl>(ws, p.off_ctl);
+    hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, st, ctl, (uint32_t)p.S, (uint32_t)p.cap_c,
+                       p.all ? 1u : 0u);
+    pm.start(st);
+    uint32_t* okey = at<uint32_t>(ws, p.off_okey);
+    uint32_t* oidx = at<uint32_t>(ws, p.off_oidx);
+    const uint32_t k = p.k;
+    if (p.mode == 1) {
+      uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
+      uint32_t* didx = at<uint32_t>(ws, p.off_didx);
+      uint32_t* Q = at<uint32_t>(ws, p.off_q);
+      uint32_t* ckey = at<uint32_t>(ws, p.off_ckey);
+      uint32_t* cidx = at<uint32_t>(ws, p.off_cidx);
+      delegate(p, keys, dkey, didx, ctl, st);
+      pm.mid(st);
+      const unsigned gD = grid_for(p.nd, 256 * 8, 1024);
+      for (int pass = 1; pass < kPasses; ++pass)
+        hipLaunchKernelGGL((k_pass<SRC_D, DT>), dim3(gD), dim3(256), 0, st, dkey, didx, p.nd, pass, 0, ctl, p.kD);
+      qualify(p, dkey, didx, ctl, Q, ckey, cidx, st);
+      const unsigned gS = grid_for((uint64_t)((k - 1) / p.beta) + 1, 4, 2048);
+      if (p.vec)
+        hipLaunchKernelGGL((k_scan<DT, true>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
+      else
+        hipLaunchKernelGGL((k_scan<DT, false>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
+      if (filter_only) return;
+      const bool may_be_big = p.cap_c > (uint64_t)kSmallCap;
+      hipLaunchKernelGGL((k_final_small<SRC_C, DT>), dim3(1), dim3(1024), 0, st, ckey, cidx, (uint64_t)0,
+                         may_be_big ? 1 : 0, k, ctl, out_vals, out_idx, out_kth);
+      if (!may_be_big) return;
+      const unsigned gC = grid_for(p.cap_c, 256 * 8, 1024);
+      for (int pass = 0; pass < kPasses; ++pass)
+        hipLaunchKernelGGL((k_pass<SRC_C, DT>), dim3(gC), dim3(256), 0, st, ckey, cidx, (uint64_t)0, pass, 2, ctl, k);
+      if (kth_only) {
+        hipLaunchKernelGGL((k_kth_from_sel<DT>), dim3(1), dim3(64), 0, st, 2, ctl, out_kth);
+        return;
+      }
+      hipLaunchKernelGGL((k_compact<SRC_C, DT>), dim3(gC), dim3(256), 0, st, ckey, cidx, (uint64_t)0, 2, k, ctl, okey,
+                         oidx);
+      if (k <= (uint32_t)kSmallCap)
+        hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 2, k,
+                           ctl, out_vals, out_idx, out_kth);
+      else
+        big_sort(p, ws, out_vals, out_idx, out_kth, st);
+    } else {
+      if (p.n <= (uint64_t)kSmallCap) {
+        hipLaunchKernelGGL((k_final_small<SRC_V, DT>), dim3(1), dim3(1024), 0, st, keys, (const uint32_t*)nullptr,
+                           p.n, 0, k, ctl, out_vals, out_idx, out_kth);
+        return;
+      }
+      const unsigned gV = grid_for(p.n, 256 * 16, 2048);
+      for (int pass = 0; pass < kPasses; ++pass) {
+        hipLaunchKernelGGL((k_pass<SRC_V, DT>), dim3(gV), dim3(256), 0, st, keys, (const uint32_t*)nullptr, p.n, pass,
+                           0, ctl, k);
+        if (pass == 0) pm.mid(st);
+      }
+      if (kth_only) {
+        hipLaunchKernelGGL((k_kth_from_sel<DT>), dim3(1), dim3(64), 0, st, 0, ctl, out_kth);
+        return;
+      }
+      hipLaunchKernelGGL((k_compact<SRC_V, DT>), dim3(gV), dim3(256), 0, st, keys, (const uint32_t*)nullptr, p.n, 0,
+                         k, ctl, okey, oidx);
+      if (k <= (uint32_t)kSmallCap)
+        hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 0, k,
+                           ctl, out_vals, out_idx, out_kth);
+      else
+        big_sort(p, ws, out_vals, out_idx, out_kth, st);
+    }
+  }
+};
+
+template <int DT>
+__global__ void k_decode_inplace(uint32_t* v, uint64_t m) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = dec<DT>(v[i]);
+}
+
+int check_args(const void* keys, uint64_t n, uint32_t k, int dtype) {
+  if (!keys) return DRTOPK_EINVAL;
+  if (n == 0 || n >= (1ull << 32)) return DRTOPK_EINVAL;
+  if (k == 0 || (uint64_t)k > n) return DRTOPK_EINVAL;
+  if (dtype != DRTOPK_U32 && dtype != DRTOPK_F32) return DRTOPK_EINVAL;
+  return DRTOPK_OK;
+}
+
+uint32_t host_dec(int dt, uint32_t u) { return dt == DT_F32 ? u ^ (((u >> 31) - 1u) | 0x80000000u) : u; }
+
+// Runs the whole path; `fn` (optional) runs under the workspace lock after the
+// enqueue, with the plan and workspace pointer.
+template <typename F>
+int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
+               void* out_kth, bool kth_only, const drtopk_options_t* opt, void* stream, F&& after,
+               bool filter_only = false) {
+  int st = check_args(keys, n, k, dtype);
+  if (st) return st;
+  Plan p;
+  st = make_plan(keys, n, k, dtype, opt, &p);
+  if (st) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  Workspace* ws = workspace_entry(dev, stream);
+  if (!ws) return DRTOPK_ENOMEM;
+  std::lock_guard<std::mutex> g(ws->mu);
+  st = ensure_bytes(ws, p.total);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t* kp = static_cast<const uint32_t*>(keys);
+  if (dtype == DRTOPK_F32)
+    Runner<DT_F32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
+                        kth_only, filter_only, s);
+  else
+    Runner<DT_U32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
+                        kth_only, filter_only, s);
+  if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+  return after(p, ws->ptr, s);
+}
+
+int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
+  if (!stats) return DRTOPK_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
+  Ctl h;
+  if (hipMemcpy(&h, at<Ctl>(ws, p.off_ctl), sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return DRTOPK_EDEVICE;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->mode = p.mode;
+  stats->alpha = p.alpha;
+  stats->beta = p.beta;
+  stats->subranges = p.S;
+  stats->delegates = p.nd;
+  stats->scanned = h.nq;
+  stats->candidates = p.mode == 1 ? h.nc : p.n;
+  stats->t_key_bits = p.mode == 1 ? host_dec(p.dt, (uint32_t)(h.selD.prefix >> 32)) : 0;
+  stats->t_idx = p.mode == 1 ? ~(uint32_t)h.selD.prefix : 0;
+  if (h.err) return DRTOPK_EDEVICE;
+  return DRTOPK_OK;
+}
+
+}  // namespace
+}  // namespace drtopk
+
+using namespace drtopk;
+
+extern "C" {
+
+int topk_select_ex(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
+                   const drtopk_options_t* opt, drtopk_stats_t* stats, void* stream) {
+  if (!out_vals) return DRTOPK_EINVAL;
+  try {
+    return run_common(keys, n, k, dtype, out_vals, out_idx, nullptr, false, opt, stream,
+                      [&](const Plan& p, void* ws, hipStream_t s) { return fill_stats(p, ws, s, stats); });
+  } catch (...) {
+    return DRTOPK_EDEVICE;
+  }
+}
+
+int topk_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
+                void* stream) {
+  return topk_select_ex(keys, n, k, dtype, out_vals, out_idx, nullptr, nullptr, stream);
+}
+
+int kth_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_kth, void* stream) {
+  if (!out_kth) return DRTOPK_EINVAL;
+  try {
+    return run_common(keys, n, k, dtype, nullptr, nullptr, out_kth, true, nullptr, stream,
+                      [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
+  } catch (...) {
+    return DRTOPK_EDEVICE;
+  }
+}
+
+int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream) {
+  if (count && !problems) return DRTOPK_EINVAL;
+  for (uint32_t i = 0; i < count; ++i) {
+    const drtopk_problem_t& q = problems[i];
+    if (!q.out_vals && !q.out_kth) return DRTOPK_EINVAL;
+    int st = check_args(q.keys, q.n, q.k, (int)q.dtype);
+    if (st) return st;
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    const drtopk_problem_t& q = problems[i];
+    int st;
+    try {
+      if (q.out_vals)
+        st = run_common(q.keys, q.n, q.k, (int)q.dtype, q.out_vals, q.out_idx, q.out_kth, false, nullptr, stream,
+                        [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
+      else
+        st = run_common(q.keys, q.n, q.k, (int)q.dtype, nullptr, nullptr, q.out_kth, true, nullptr, stream,
+                        [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
+    } catch (...) {
+      st = DRTOPK_EDEVICE;
+    }
+    if (st) return st;
+  }
+  return DRTOPK_OK;
+}
+
+int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int beta, void* out_dkeys,
+                     uint32_t* out_didx, void* stream) {
+  if (!out_dkeys || !out_didx) return DRTOPK_EINVAL;
+  int st = check_args(keys, n, 1, dtype);
+  if (st) return st;
+  if (alpha < 0 || alpha > 24 || !valid_beta(beta)) return DRTOPK_EINVAL;
+  drtopk_options_t o{alpha, beta, 1, 0};
+  Plan p;
+  st = make_plan(keys, n, 1, dtype, &o, &p);
+  if (st) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  Workspace* ws = workspace_entry(dev, stream);
+  if (!ws) return DRTOPK_ENOMEM;
+  std::lock_guard<std::mutex> lock(ws->mu);
+  st = ensure_bytes(ws, p.total);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Ctl* ctl = at<Ctl>(ws->ptr, p.off_ctl);
+  const uint32_t* kp = static_cast<const uint32_t*>(keys);
+  uint32_t* dk = static_cast<uint32_t*>(out_dkeys);
+  hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, s, ctl, (uint32_t)p.S, (uint32_t)p.cap_c, 0u);
+  const unsigned g = grid_for(p.nd, 256 * 4, 4096);
+  if (dtype == DRTOPK_F32) {
+    Runner<DT_F32>::delegate(p, kp, dk, out_didx, ctl, s);
+    hipLaunchKernelGGL((k_decode_inplace<DT_F32>), dim3(g), dim3(256), 0, s, dk, p.nd);
+  } else {
+    Runner<DT_U32>::delegate(p, kp, dk, out_didx, ctl, s);
+  }
+  if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+  return DRTOPK_OK;
+}
+
+int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta, uint32_t* out_pos,
+                      uint64_t cap, uint64_t* count, void* stream) {
+  if (!out_pos || !count) return DRTOPK_EINVAL;
+  if (alpha < 0 || alpha > 24 || !valid_beta(beta)) return DRTOPK_EINVAL;
+  drtopk_options_t o{alpha, beta, 1, 0};
+  try {
+    return run_common(keys, n, k, dtype, nullptr, nullptr, nullptr, true, &o, stream,
+                      [&](const Plan& p, void* ws, hipStream_t s) {
+                        if (hipStreamSynchronize(s) != hipSuccess) return (int)DRTOPK_EDEVICE;
+                        uint32_t nc = 0;
+                        if (hipMemcpy(&nc, &at<Ctl>(ws, p.off_ctl)->nc, 4, hipMemcpyDeviceToHost) != hipSuccess)
+                          return (int)DRTOPK_EDEVICE;
+                        *count = nc;
+                        if (nc > cap) return (int)DRTOPK_EINVAL;
+                        if (nc && hipMemcpy(out_pos, at<uint32_t>(ws, p.off_cidx), (size_t)nc * 4,
+                                            hipMemcpyDeviceToDevice) != hipSuccess)
+                          return (int)DRTOPK_EDEVICE;
+                        return (int)DRTOPK_OK;
+                      },
+                      true);
+  } catch (...) {
+    return DRTOPK_EDEVICE;
+  }
+}
+
+int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out) {
+  if (!out) return DRTOPK_EINVAL;
+  static const uint32_t dummy[4] = {0, 0, 0, 0};
+  int st = check_args(dummy, n, k, dtype);
+  if (st) return st;
+  Plan p;
+  st = make_plan(dummy, n, k, dtype, nullptr, &p);
+  if (st) return st;
+  out->alpha = p.alpha;
+  out->beta = p.beta;
+  out->mode = p.mode;
+  out->reserved = 0;
+  return DRTOPK_OK;
+}
+
+int drtopk_release_workspace(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return DRTOPK_EDEVICE;
+  std::lock_guard<std::mutex> g(g_mu);
+  for (auto it = g_ws.begin(); it != g_ws.end();) {
+    if (it->first.first == dev) {
+      std::lock_guard<std::mutex> g2(it->second->mu);
+      if (it->second->ptr) (void)hipFree(it->second->ptr);
+      it->second->ptr = nullptr;
+      it->second->bytes = 0;
+      ++it;
+    } else {
+      ++it;
+    }
+  }
+  return DRTOPK_OK;
+}
+
+int drtopk_timing_enable(int on) {
+  std::lock_guard<std::mutex> g(g_timing.mu);
+  g_timing.on = on != 0;
+  return DRTOPK_OK;
+}
+
+int drtopk_timing_read(double* delegate_ms, double* tail_ms, uint64_t* calls) {
+  std::vector<Timing::Rec> recs;
+  {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    recs.swap(g_timing.pending);
+  }
+  double d = 0, t = 0;
+  int st = DRTOPK_OK;
+  for (auto& r : recs) {
+    float x = 0, y = 0;
+    if (hipEventSynchronize(r.c) != hipSuccess || hipEventElapsedTime(&x, r.a, r.b) != hipSuccess ||
+        hipEventElapsedTime(&y, r.b, r.c) != hipSuccess)
+      st = DRTOPK_EDEVICE;
+    d += x;
+    t += y;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    for (auto& r : recs) {
+      g_timing.pool.push_back(r.a);
+      g_timing.pool.push_back(r.b);
+      g_timing.pool.push_back(r.c);
+    }
+  }
+  if (delegate_ms) *delegate_ms = d;
+  if (tail_ms) *tail_ms = t;
+  if (calls) *calls = recs.size();
+  return st;
+}
+
+const char* drtopk_status_string(int status) {
+  switch (status) {
+    case DRTOPK_OK: return "ok";
+    case DRTOPK_EINVAL: return "invalid argument";
+    case DRTOPK_ENOMEM: return "out of device memory";
+    case DRTOPK_EDEVICE: return "device error";
+    case DRTOPK_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* drtopk_version(void) { return "drtopk 0.1 (gfx950)"; }
+
+}  // extern "C"

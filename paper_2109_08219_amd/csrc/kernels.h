@@ -1,0 +1,581 @@
+// HIP kernels of the delegate-centric top-k path (gfx950, wave64).
+//
+//   k_delegate*   delegate vector (Rules 1 and 3): one streaming pass over V
+//                 with 128-bit non-temporal loads, per-subrange top-beta, and
+//                 the first radix digit of the delegates' histogram fused in
+//   k_pass        one MSD digit of a radix select over composites (8 passes
+//                 would do for 32-bit keys; 6 digits of 11/11/10 bits cover the
+//                 64-bit key+position composite)
+//   k_qualify     Rule 3 as a threshold test per subrange; delegates of the
+//                 other subranges at or above the threshold go straight to
+//                 the survivors
+//   k_scan        re-reads only the qualifying subranges, keeps elements at or
+//                 above the threshold (Rule 2), wave-ballot compaction
+//   k_final_small survivors sorted in LDS by one workgroup
+//   k_compact / k_blocksort / k_merge   large-k output: exact k, then a sort
+#pragma once
+
+#include "internal.h"
+
+namespace drtopk {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// top-beta list of composites held by one lane (descending)
+template <int BETA>
+struct TopB {
+  uint64_t c[BETA];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) c[j] = 0;
+  }
+  __device__ __forceinline__ void push(uint64_t x) {
+    if constexpr (BETA == 1) {
+      c[0] = x > c[0] ? x : c[0];
+    } else {
+      bool g[BETA];
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) g[j] = x > c[j];
+#pragma unroll
+      for (int j = BETA - 1; j >= 1; --j) c[j] = g[j] ? (g[j - 1] ? c[j - 1] : x) : c[j];
+      c[0] = g[0] ? x : c[0];
+    }
+  }
+  // Replace this list by the top-BETA of (this list, the list of lane ^ m).
+  // Max of one list against the other reversed is bitonic and holds the top
+  // BETA; half-cleaners then sort it.
+  __device__ __forceinline__ void merge_xor(int m) {
+    uint64_t o[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) o[j] = shfl_xor64(c[j], m);
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) c[j] = c[j] > o[BETA - 1 - j] ? c[j] : o[BETA - 1 - j];
+#pragma unroll
+    for (int s = BETA / 2; s >= 1; s >>= 1) {
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+        if ((j & s) == 0) {
+          uint64_t a = c[j], b = c[j + s];
+          c[j] = a > b ? a : b;
+          c[j + s] = a > b ? b : a;
+        }
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// block helpers (blockDim.x == 256)
+
+// Finds, in a 2048-bin histogram read from global memory, the bin holding the
+// rank-th largest entry (bins scanned from the top).  s_out = {bin, rank within
+// bin, found}.
+__device__ inline void block_select_bucket(const uint32_t* gh, uint32_t rank, uint32_t* s_scan,
+                                           uint32_t* s_out) {
+  const int t = threadIdx.x;
+  uint32_t c[8], sum = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    c[j] = atomic_load_u32(&gh[kBins - 1 - 8 * t - j]);
+    sum += c[j];
+  }
+  s_scan[t] = sum;
+  if (t == 0) { s_out[0] = 0; s_out[1] = 0; s_out[2] = 0; }
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t x = t >= off ? s_scan[t - off] : 0u;
+    __syncthreads();
+    s_scan[t] += x;
+    __syncthreads();
+  }
+  uint32_t incl = s_scan[t], excl = incl - sum;
+  if (excl < rank && rank <= incl) {
+    uint32_t cum = excl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (cum + c[j] >= rank) {
+        s_out[0] = kBins - 1 - 8 * t - j;
+        s_out[1] = rank - cum;
+        s_out[2] = 1;
+        break;
+      }
+      cum += c[j];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ inline void flush_hist(const uint32_t* lh, uint32_t* gh) {
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
+    uint32_t v = lh[i];
+    if (v) atomicAdd(&gh[i], v);
+  }
+}
+
+// Completes digit pass p: the last block to finish (ticket) derives the new
+// selection state from the finished global histogram.
+__device__ inline void finish_pass(uint32_t* gh, uint32_t* ticket, Sel* sel, int p, uint32_t k,
+                                   Ctl* ctl, uint32_t* s_scan, uint32_t* s_out, int* s_last) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!*s_last) return;
+  __threadfence();
+  uint64_t prefix = 0, mask = 0;
+  uint32_t rank = k;
+  if (p > 0) {
+    prefix = sel->prefix;
+    mask = sel->mask;
+    rank = sel->rank;
+  }
+  block_select_bucket(gh, rank, s_scan, s_out);
+  if (threadIdx.x == 0) {
+    const int sh = pass_shift(p);
+    const uint64_t dm = (1ull << pass_bits(p)) - 1;
+    sel->prefix = prefix | ((uint64_t)s_out[0] << sh);
+    sel->mask = mask | (dm << sh);
+    sel->rank = s_out[1];
+    sel->found = s_out[2];
+    if (!s_out[2]) ctl->err |= 1u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// delegate vector
+
+template <int BETA>
+__device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb, uint32_t* dkey,
+                                               uint32_t* didx, uint32_t* lh) {
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    const uint32_t kk = comp_key(tb.c[j]);
+    dkey[s * BETA + j] = kk;
+    didx[s * BETA + j] = comp_pos(tb.c[j]);  // padding (composite 0) gives 0xFFFFFFFF
+    atomicAdd(&lh[kk >> 21], 1u);
+  }
+}
+
+template <int DT, bool VEC>
+__device__ __forceinline__ void load4(const uint32_t* __restrict__ keys, uint64_t p, uint32_t v[4]) {
+  if constexpr (VEC) {
+    u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + p));
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+    v[0] = keys[p]; v[1] = keys[p + 1]; v[2] = keys[p + 2]; v[3] = keys[p + 3];
+  }
+}
+
+constexpr int kUnroll = 8;  // 128-bit loads in flight per lane
+
+// Subranges of >= 256 elements: one wave per subrange, each lane folds its
+// elements into a private top-beta, then a butterfly merge across the wave.
+template <int DT, int BETA, bool VEC>
+__device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                              uint64_t wlo, uint64_t whi, bool fast,
+                                              uint32_t* dkey, uint32_t* didx, uint32_t* lh) {
+  const uint32_t lane = lane_id();
+  const uint64_t wps_mask = (1ull << (alpha - 8)) - 1;  // wave-loads per subrange - 1
+  const uint64_t nwl = (whi + 255 - wlo) >> 8;
+  TopB<BETA> tb;
+  tb.clear();
+  for (uint64_t j0 = 0; j0 < nwl; j0 += kUnroll) {
+    uint32_t v[kUnroll][4];
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, wlo + ((j0 + u) << 8) + lane * 4, v[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const uint64_t p = wlo + ((j0 + u) << 8) + lane * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[u][c] = (j0 + u < nwl && p + c < n) ? keys[p + c] : 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t j = j0 + u;
+      if (j < nwl) {
+        const uint64_t p = wlo + (j << 8) + lane * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
+        if (((j + 1) & wps_mask) == 0 || j + 1 == nwl) {
+#pragma unroll
+          for (int m = 1; m < 64; m <<= 1) tb.merge_xor(m);
+          if (lane == 0) emit_delegates<BETA>((wlo + (j << 8)) >> alpha, tb, dkey, didx, lh);
+          tb.clear();
+        }
+      }
+    }
+  }
+}
+
+// Subranges of 4..128 elements: 2^(alpha-2) lanes per subrange inside each
+// 256-element wave-load; segmented butterfly merge.
+template <int DT, int BETA, bool VEC>
+__device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                               uint64_t wlo, uint64_t whi, bool fast,
+                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh) {
+  const uint32_t lane = lane_id();
+  const uint32_t gl = 1u << (alpha - 2);  // lanes per subrange
+  const uint64_t nwl = (whi + 255 - wlo) >> 8;
+  for (uint64_t j0 = 0; j0 < nwl; j0 += kUnroll) {
+    uint32_t v[kUnroll][4];
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, wlo + ((j0 + u) << 8) + lane * 4, v[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const uint64_t p = wlo + ((j0 + u) << 8) + lane * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[u][c] = (j0 + u < nwl && p + c < n) ? keys[p + c] : 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t j = j0 + u;
+      if (j < nwl) {
+        const uint64_t p = wlo + (j << 8) + lane * 4;
+        TopB<BETA> tb;
+        tb.clear();
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
+        for (uint32_t m = 1; m < gl; m <<= 1) tb.merge_xor((int)m);
+        if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh);
+      }
+    }
+  }
+}
+
+// One block per chunk of `chunk` elements (a multiple of 4 * 2^alpha and of
+// 4 * 256 * kUnroll); each wave streams a contiguous quarter of the chunk.
+template <int DT, int BETA, bool VEC>
+__global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                                  uint64_t chunk, uint32_t* __restrict__ dkey,
+                                                  uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
+  __shared__ uint32_t lh[kBins];
+  __shared__ uint32_t s_scan[256];
+  __shared__ uint32_t s_out[4];
+  __shared__ int s_last;
+  for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+  __syncthreads();
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint64_t wlen = chunk >> 2;
+  const uint64_t wlo = (uint64_t)blockIdx.x * chunk + wave * wlen;
+  if (wlo < n) {
+    const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
+    const bool fast = (wlo + wlen <= n);
+    if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh);
+    else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh);
+  }
+  __syncthreads();
+  flush_hist(lh, ctl->histD[0]);
+  finish_pass(ctl->histD[0], &ctl->ticketD[0], &ctl->selD, 0, k, ctl, s_scan, s_out, &s_last);
+}
+
+// Subranges of 1 or 2 elements, or any alpha when the planner asks for the
+// simple form: one thread per subrange.
+template <int DT, int BETA>
+__global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restrict__ keys, uint64_t n,
+                                                         int alpha, uint64_t S, uint32_t* __restrict__ dkey,
+                                                         uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
+  __shared__ uint32_t lh[kBins];
+  __shared__ uint32_t s_scan[256];
+  __shared__ uint32_t s_out[4];
+  __shared__ int s_last;
+  for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+  __syncthreads();
+  for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < S; s += (uint64_t)gridDim.x * 256) {
+    TopB<BETA> tb;
+    tb.clear();
+    const uint64_t lo = s << alpha;
+    const uint64_t hi = (lo + (1ull << alpha)) < n ? lo + (1ull << alpha) : n;
+    for (uint64_t p = lo; p < hi; ++p) tb.push(comp(enc<DT>(keys[p]), (uint32_t)p));
+    emit_delegates<BETA>(s, tb, dkey, didx, lh);
+  }
+  __syncthreads();
+  flush_hist(lh, ctl->histD[0]);
+  finish_pass(ctl->histD[0], &ctl->ticketD[0], &ctl->selD, 0, k, ctl, s_scan, s_out, &s_last);
+}
+
+// ---------------------------------------------------------------------------
+// one digit of an MSD radix select over composites
+
+template <int SRC, int DT>
+__device__ __forceinline__ uint32_t src_key(const uint32_t* key, uint64_t i) {
+  if constexpr (SRC == SRC_V) return enc<DT>(key[i]);
+  else return key[i];
+}
+template <int SRC>
+__device__ __forceinline__ uint32_t src_pos(const uint32_t* idx, uint64_t i) {
+  if constexpr (SRC == SRC_V) return (uint32_t)i;
+  else return idx[i];
+}
+
+// gate: 0 always run, 1 run only if survivors <= kSmallCap, 2 only if > kSmallCap
+__device__ __forceinline__ bool gated_off(const Ctl* ctl, int gate) {
+  if (gate == 0) return false;
+  const bool small = clamp_nc(ctl) <= (uint32_t)kSmallCap;
+  return gate == 1 ? !small : small;
+}
+
+template <int SRC, int DT>
+__global__ __launch_bounds__(256) void k_pass(const uint32_t* __restrict__ key, const uint32_t* __restrict__ idx,
+                                              uint64_t count_static, int p, int gate, Ctl* ctl, uint32_t k) {
+  __shared__ uint32_t lh[kBins];
+  __shared__ uint32_t s_scan[256];
+  __shared__ uint32_t s_out[4];
+  __shared__ int s_last;
+  if (gated_off(ctl, gate)) return;
+  const bool isD = (SRC == SRC_D);
+  Sel* sel = isD ? &ctl->selD : &ctl->selC;
+  uint32_t* gh = isD ? ctl->histD[p] : ctl->histC[p];
+  uint32_t* ticket = isD ? &ctl->ticketD[p] : &ctl->ticketC[p];
+  const uint64_t count = (SRC == SRC_C) ? (uint64_t)clamp_nc(ctl) : count_static;
+  uint64_t prefix = 0, mask = 0;
+  if (p > 0) { prefix = sel->prefix; mask = sel->mask; }
+  for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+  __syncthreads();
+  const int sh = pass_shift(p);
+  const uint32_t dm = (1u << pass_bits(p)) - 1;
+  const uint32_t kmask = (uint32_t)(mask >> 32), kpref = (uint32_t)(prefix >> 32);
+  const uint32_t imask = (uint32_t)mask, ipref = (uint32_t)prefix;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (uint64_t)gridDim.x * 256) {
+    const uint32_t kk = src_key<SRC, DT>(key, i);
+    if ((kk & kmask) != kpref) continue;
+    uint64_t c = (uint64_t)kk << 32;
+    if (p >= 3) {
+      const uint32_t ip = ~src_pos<SRC>(idx, i);
+      if ((ip & imask) != ipref) continue;
+      c |= ip;
+    }
+    atomicAdd(&lh[(uint32_t)(c >> sh) & dm], 1u);
+  }
+  __syncthreads();
+  flush_hist(lh, gh);
+  finish_pass(gh, ticket, sel, p, k, ctl, s_scan, s_out, &s_last);
+}
+
+// ---------------------------------------------------------------------------
+// Rule 3 per subrange: re-read s only if its beta-th delegate ranks strictly
+// above the threshold t; otherwise keep its delegates that rank at or above t.
+
+template <int BETA>
+__global__ __launch_bounds__(256) void k_qualify(const uint32_t* __restrict__ dkey, const uint32_t* __restrict__ didx,
+                                                 uint64_t S, Ctl* ctl, uint32_t* __restrict__ Q,
+                                                 uint32_t* __restrict__ ckey, uint32_t* __restrict__ cidx) {
+  const uint64_t t = ctl->all ? 0ull : ctl->selD.prefix;
+  const uint32_t cap_q = ctl->cap_q, cap_c = ctl->cap_c;
+  for (uint64_t s0 = (uint64_t)blockIdx.x * 256; s0 < S; s0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t s = s0 + threadIdx.x;
+    const bool ok = s < S;
+    uint64_t dc = 0;
+    if (ok) dc = comp(dkey[s * BETA + BETA - 1], didx[s * BETA + BETA - 1]);
+    const bool scan = ok && dc > t;
+    const uint32_t slot = wave_append(scan, &ctl->nq);
+    if (scan) {
+      if (slot < cap_q) Q[slot] = (uint32_t)s;
+      else ctl->err |= 8u;
+    }
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) {
+      uint64_t c = 0;
+      if (ok && !scan) c = comp(dkey[s * BETA + j], didx[s * BETA + j]);
+      const bool take = c != 0 && c >= t;
+      const uint32_t sl = wave_append(take, &ctl->nc);
+      if (take) {
+        if (sl < cap_c) { ckey[sl] = comp_key(c); cidx[sl] = comp_pos(c); }
+        else ctl->err |= 16u;
+      }
+    }
+  }
+}
+
+// Re-read the qualifying subranges (one wave each) and keep every element
+// ranked at or above t (Rule 2's filter, inclusive).
+template <int DT, bool VEC>
+__global__ __launch_bounds__(256) void k_scan(const uint32_t* __restrict__ keys, uint64_t n, int alpha, Ctl* ctl,
+                                              const uint32_t* __restrict__ Q, uint32_t* __restrict__ ckey,
+                                              uint32_t* __restrict__ cidx) {
+  const uint32_t nq = clamp_nq(ctl);
+  const uint32_t cap_c = ctl->cap_c;
+  const uint64_t t = ctl->all ? 0ull : ctl->selD.prefix;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * 4;
+  for (uint32_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < nq; q += nw) {
+    const uint64_t lo = (uint64_t)Q[q] << alpha;
+    const uint64_t hi = lo + (1ull << alpha) < n ? lo + (1ull << alpha) : n;
+    for (uint64_t b = lo; b < hi; b += 256) {
+      const uint64_t p = b + lane * 4;
+      uint32_t v[4];
+      if (VEC && alpha >= 2 && p + 4 <= hi) {
+        load4<DT, true>(keys, p, v);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = p + c < hi ? keys[p + c] : 0u;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint64_t cc = comp(enc<DT>(v[c]), (uint32_t)(p + c));
+        const bool take = (p + c < hi) && cc >= t;
+        const uint32_t sl = wave_append(take, &ctl->nc);
+        if (take) {
+          if (sl < cap_c) { ckey[sl] = comp_key(cc); cidx[sl] = (uint32_t)(p + c); }
+          else ctl->err |= 16u;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// outputs
+
+template <int SRC, int DT>
+__device__ __forceinline__ uint64_t src_comp(const uint32_t* key, const uint32_t* idx, uint64_t i) {
+  return comp(src_key<SRC, DT>(key, i), src_pos<SRC>(idx, i));
+}
+
+template <int DT>
+__device__ __forceinline__ void write_out(uint64_t c, uint32_t r, uint32_t k, uint32_t* out_vals,
+                                          uint32_t* out_idx, uint32_t* out_kth) {
+  const uint32_t v = dec<DT>(comp_key(c));
+  if (out_vals) out_vals[r] = v;
+  if (out_idx) out_idx[r] = comp_pos(c);
+  if (out_kth && r == k - 1) *out_kth = v;
+}
+
+// One workgroup: all `count` (<= kSmallCap) entries sorted in LDS, first k written.
+template <int SRC, int DT>
+__global__ __launch_bounds__(1024) void k_final_small(const uint32_t* __restrict__ key,
+                                                      const uint32_t* __restrict__ idx, uint64_t count_static,
+                                                      int gate, uint32_t k, Ctl* ctl, uint32_t* out_vals,
+                                                      uint32_t* out_idx, uint32_t* out_kth) {
+  __shared__ uint64_t buf[kSmallCap];
+  if (gated_off(ctl, gate)) return;
+  const uint64_t count = (SRC == SRC_C) ? (uint64_t)clamp_nc(ctl) : count_static;
+  if (count > (uint64_t)kSmallCap || count < k) {
+    if (threadIdx.x == 0) ctl->err |= 2u;
+    return;
+  }
+  uint32_t P = 64;
+  while (P < count) P <<= 1;
+  for (uint32_t i = threadIdx.x; i < P; i += 1024) buf[i] = i < count ? src_comp<SRC, DT>(key, idx, i) : 0ull;
+  __syncthreads();
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < (P >> 1); i += 1024) {
+        const uint32_t lo = 2 * i - (i & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const uint64_t a = buf[lo], b = buf[hi];
+        if ((a < b) == desc) { buf[lo] = b; buf[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t r = threadIdx.x; r < k; r += 1024) write_out<DT>(buf[r], r, k, out_vals, out_idx, out_kth);
+}
+
+// Exactly the k entries ranked at or above the k-th (selC) -> okey/oidx.
+template <int SRC, int DT>
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ key, const uint32_t* __restrict__ idx,
+                                                 uint64_t count_static, int gate, uint32_t k, Ctl* ctl,
+                                                 uint32_t* __restrict__ okey, uint32_t* __restrict__ oidx) {
+  if (gated_off(ctl, gate)) return;
+  const uint64_t count = (SRC == SRC_C) ? (uint64_t)clamp_nc(ctl) : count_static;
+  const uint64_t T = ctl->selC.prefix;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < count; i0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t i = i0 + threadIdx.x;
+    uint64_t c = 0;
+    if (i < count) c = src_comp<SRC, DT>(key, idx, i);
+    const bool take = i < count && c >= T;
+    const uint32_t sl = wave_append(take, &ctl->nout);
+    if (take) {
+      if (sl < k) { okey[sl] = comp_key(c); oidx[sl] = comp_pos(c); }
+      else ctl->err |= 4u;
+    }
+  }
+}
+
+// k-th value straight from the survivor select (k-selection needs no sort).
+template <int DT>
+__global__ void k_kth_from_sel(int gate, Ctl* ctl, uint32_t* out_kth) {
+  if (gated_off(ctl, gate) || !out_kth) return;
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out_kth = dec<DT>((uint32_t)(ctl->selC.prefix >> 32));
+}
+
+// Sort tiles of kSortTile composites in LDS (descending); pads are 0.
+__global__ __launch_bounds__(1024) void k_blocksort(const uint32_t* __restrict__ okey,
+                                                    const uint32_t* __restrict__ oidx, uint32_t k,
+                                                    uint64_t* __restrict__ A) {
+  __shared__ uint64_t buf[kSortTile];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (uint32_t j = threadIdx.x; j < kSortTile; j += 1024) {
+    const uint64_t i = base + j;
+    buf[j] = i < k ? comp(okey[i], oidx[i]) : 0ull;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= kSortTile; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < kSortTile / 2; i += 1024) {
+        const uint32_t lo = 2 * i - (i & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const uint64_t a = buf[lo], b = buf[hi];
+        if ((a < b) == desc) { buf[lo] = b; buf[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t j = threadIdx.x; j < kSortTile; j += 1024) A[base + j] = buf[j];
+}
+
+// Merge pairs of sorted runs of length `run` by rank: an element's output slot
+// is its slot in its own run plus the number of partner-run elements placed
+// before it (strictly greater for the left run, greater-or-equal for the right
+// run, so equal pads stay stable).  The last merge writes the outputs.
+template <int DT>
+__global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ A, uint64_t* __restrict__ B, uint64_t M,
+                                               uint64_t run, int last, uint32_t k, uint32_t* out_vals,
+                                               uint32_t* out_idx, uint32_t* out_kth) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const uint64_t pair = i / (2 * run) * (2 * run);
+  const uint64_t within = i - pair;
+  const bool left = within < run;
+  const uint64_t own = left ? within : within - run;
+  const uint64_t* other = A + (left ? pair + run : pair);
+  const uint64_t x = A[i];
+  uint64_t lo = 0, hi = run;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    const uint64_t y = other[mid];
+    const bool before = left ? (y > x) : (y >= x);
+    if (before) lo = mid + 1;
+    else hi = mid;
+  }
+  const uint64_t out = pair + own + lo;
+  if (last) {
+    if (out < k) write_out<DT>(x, (uint32_t)out, k, out_vals, out_idx, out_kth);
+  } else {
+    B[out] = x;
+  }
+}
+
+__global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t all) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
+  const uint32_t nw = offsetof(Ctl, cap_q) / 4;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) w[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->cap_q = cap_q;
+    ctl->cap_c = cap_c;
+    ctl->all = all;
+  }
+}
+
+}  // namespace drtopk

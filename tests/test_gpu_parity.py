@@ -1,0 +1,261 @@
+"""HIP path vs the oracle, element by element, through the C-ABI.
+
+Sizes span several delegate chunks, subrange shapes and ragged tails; the
+workloads follow the paper's uniform dataset plus this project's normal,
+sorted and heavy-duplicate stand-ins; the full-size cases run the planner's
+choice at N = 2^30 (and 2^29 for the adversarial inputs) and are checked by
+invariants that fix the answer uniquely.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import stages
+from checks import check_exact, check_invariants, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+drt = pytest.importorskip("paper_2109_08219_amd")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run_topk(x, k, **kw):
+    vals, idx = drt.topk_select(dev(x), k, **kw)[:2]
+    torch.cuda.synchronize()
+    return to_np(vals), to_np(idx)
+
+
+KINDS = ["uniform_u32", "normal_f32", "sorted_f32", "heavydup_u32"]
+
+
+def ks_for(n):
+    return sorted({k for k in (1, 2, 33, 1024, 8192, 8193, 20000, n) if 1 <= k <= n})
+
+
+def test_config_small_uniform_k1024():
+    """N = 2^20 uint32 uniform, k = 1024: sorted values, positions and k-th value."""
+    x = synth.uniform_u32(1 << 20, synth.DEFAULT_SEED)
+    say("n=2^20 u32 uniform k=1024")
+    vals, idx = run_topk(x, 1024)
+    check_exact(x, 1024, "u32", vals, idx, "config small")
+    kth = to_np(drt.kth_select(dev(x), 1024))
+    assert int(kth[0]) == int(oracle.kth_value(x, 1024, "u32"))
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_sizes_and_k(kind):
+    for n in (1, 3, 64, 1000, 8192, 8193, 65537, 300007, (1 << 20) + 13):
+        x, dt = synth.keys(kind, n, 1000 + n)
+        for k in ks_for(n):
+            say(kind, "n", n, "k", k)
+            vals, idx = run_topk(x, k)
+            check_exact(x, k, dt, vals, idx, f"{kind} n={n} k={k}")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_alpha_beta_invariance(kind):
+    n = (1 << 18) + 77
+    x, dt = synth.keys(kind, n, 7)
+    for k in (1, 100, 5000):
+        want = oracle.topk_reference(x, k, dt)
+        for alpha in (0, 1, 2, 3, 5, 7, 8, 9, 12):
+            for beta in (1, 2, 4, 8):
+                say(kind, "k", k, "alpha", alpha, "beta", beta)
+                vals, idx = run_topk(x, k, alpha=alpha, beta=beta, mode=1)
+                assert (idx.view(np.uint32) == want[1]).all(), (kind, k, alpha, beta)
+                assert (vals.view(np.uint32) == want[0].view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("kind", ["uniform_u32", "normal_f32", "heavydup_u32", "sorted_f32"])
+def test_delegate_vector_stage(kind):
+    for n in (1000, (1 << 16) + 5):
+        x, dt = synth.keys(kind, n, 11)
+        for alpha in (0, 1, 2, 4, 7, 8, 10):
+            for beta in (1, 2, 4, 8):
+                say("delegates", kind, n, alpha, beta)
+                dk, di = drt.delegates(dev(x), alpha, beta)
+                torch.cuda.synchronize()
+                got_i = to_np(di).view(np.uint32).astype(np.int64)
+                _, want_i = stages.delegates(x, dt, alpha, beta)
+                assert (got_i == want_i).all(), (kind, n, alpha, beta)
+                real = want_i != oracle.INVALID_INDEX
+                gk = to_np(dk).view(np.uint32)
+                assert (gk[real] == x.view(np.uint32)[want_i[real]]).all()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_candidate_stage(kind):
+    n = (1 << 17) + 3
+    x, dt = synth.keys(kind, n, 12)
+    for alpha, beta, k in [(4, 1, 50), (6, 2, 500), (8, 1, 3000), (9, 4, 3000), (5, 8, 64), (2, 1, 7)]:
+        say("candidates", kind, alpha, beta, k)
+        got = np.sort(to_np(drt.candidates(dev(x), k, alpha, beta)).view(np.uint32).astype(np.int64))
+        _, _, info = stages.method_topk(x, k, dt, alpha, beta)
+        assert (got == info["candidates"]).all(), (kind, alpha, beta, k, got.size, info["candidates"].size)
+
+
+def test_plain_radix_mode():
+    for kind in ("uniform_u32", "normal_f32", "heavydup_u32"):
+        for n, k in [(5000, 4999), (100000, 17), (100000, 9000), (300001, 150000)]:
+            x, dt = synth.keys(kind, n, 5)
+            say("plain radix", kind, n, k)
+            vals, idx = run_topk(x, k, mode=2)
+            check_exact(x, k, dt, vals, idx, f"plain {kind} {n} {k}")
+
+
+def test_float_specials():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(50000).astype(np.float32)
+    specials = np.array([0x7FC00000, 0xFFC00000, 0x7F800000, 0xFF800000, 0x80000000, 0x00000000,
+                         0x00000001, 0x80000001, 0x7F7FFFFF, 0xFF7FFFFF, 0x7FFFFFFF, 0xFFFFFFFF],
+                        dtype=np.uint32).view(np.float32)
+    pos = rng.integers(0, x.shape[0], size=600)
+    x[pos] = specials[rng.integers(0, specials.shape[0], size=600)]
+    for k in (1, 5, 300, 2000, 50000):
+        say("float specials k", k)
+        vals, idx = run_topk(x, k)
+        check_exact(x, k, "f32", vals, idx, f"specials k={k}")
+        vals, idx = run_topk(x, k, alpha=4, beta=2, mode=1)
+        check_exact(x, k, "f32", vals, idx, f"specials delegates k={k}")
+
+
+def test_unaligned_input():
+    x = synth.uniform_u32((1 << 20) + 3, 21)
+    t = dev(x)
+    for off in (1, 2, 3):
+        sub = t[off:]
+        say("unaligned offset", off)
+        vals, idx = drt.topk_select(sub, 777)
+        check_exact(x[off:], 777, "u32", to_np(vals), to_np(idx), f"offset {off}")
+
+
+def test_side_stream_and_repeat():
+    x = synth.normal_f32((1 << 21) + 5, 31)
+    t = dev(x)
+    s = torch.cuda.Stream()
+    want = oracle.topk_reference(x, 4096, "f32")
+    for rep in range(3):
+        say("side stream rep", rep)
+        with torch.cuda.stream(s):
+            vals, idx = drt.topk_select(t, 4096, stream=s)
+        s.synchronize()
+        assert (to_np(idx).view(np.uint32) == want[1]).all()
+
+
+def test_kth_select_matches():
+    for kind in KINDS:
+        for n, k in [(100, 37), (70000, 1), (70000, 9999), ((1 << 20) + 1, 20000)]:
+            x, dt = synth.keys(kind, n, 41)
+            say("kth", kind, n, k)
+            got = to_np(drt.kth_select(dev(x), k))[0]
+            assert got.view(np.uint32) == np.asarray(oracle.kth_value(x, k, dt)).view(np.uint32)
+
+
+def test_batched_equals_single():
+    probs, hosts = [], []
+    for i in range(24):
+        n = int(synth.log_uniform_int(1, 10, 18, 500 + i)[0])
+        kind = "uniform_u32" if i % 2 == 0 else "normal_f32"
+        x, dt = synth.keys(kind, n, 600 + i)
+        k = 1 + int(synth.unit_uniform(1, 700 + i)[0] * min(n, 2048))
+        probs.append((dev(x), k))
+        hosts.append((x, dt, k))
+    say("batched 24")
+    outs = drt.topk_select_batched(probs)
+    torch.cuda.synchronize()
+    for (x, dt, k), (v, ix, kth) in zip(hosts, outs):
+        check_exact(x, k, dt, to_np(v), to_np(ix), "batched")
+        assert to_np(kth).view(np.uint32)[0] == to_np(v).view(np.uint32)[k - 1]
+
+
+def test_errors_on_gpu():
+    t = dev(synth.uniform_u32(100, 1))
+    with pytest.raises(drt.DrTopkError):
+        drt.topk_select(t, 0)
+    with pytest.raises(drt.DrTopkError):
+        drt.topk_select(t, 101)
+    with pytest.raises(ValueError):
+        drt.topk_select(t.to(torch.float64), 3)
+    with pytest.raises(TypeError):
+        drt.topk_select(t.view(torch.int32), 3)
+    with pytest.raises(ValueError):
+        drt.topk_select(t.cpu(), 3)
+
+
+# ---------------------------------------------------------------------------
+# full sizes, planner's launch configuration (the one bench.py times)
+
+@pytest.fixture(scope="module")
+def full_u32():
+    return synth.uniform_u32(1 << 30, synth.DEFAULT_SEED)
+
+
+@pytest.fixture(scope="module")
+def full_f32():
+    return synth.normal_f32(1 << 30, synth.DEFAULT_SEED)
+
+
+def _full_case(x, dt, ks):
+    t = dev(x)
+    full = oracle.rank_key(x, dt)
+    for k in ks:
+        say("full size", dt, "k", k)
+        vals, idx, st = drt.topk_select(t, k, stats=True)
+        say("  alpha", st.alpha, "beta", st.beta, "scanned", st.scanned, "candidates", st.candidates)
+        check_invariants_fast(x, full, k, dt, to_np(vals), to_np(idx))
+    del t
+    torch.cuda.empty_cache()
+
+
+def check_invariants_fast(x, full, k, dt, vals, idx):
+    gi = idx.view(np.uint32).astype(np.int64)
+    assert np.unique(gi).shape[0] == k
+    assert (x.view(np.uint32)[gi] == vals.view(np.uint32)).all()
+    rk = full[gi]
+    assert ((rk[:-1] > rk[1:]) | ((rk[:-1] == rk[1:]) & (gi[:-1] < gi[1:]))).all()
+    kth = rk[-1]
+    greater = int(np.count_nonzero(full > kth))
+    eq = np.flatnonzero(full == kth)
+    assert greater < k <= greater + eq.shape[0]
+    tied = np.sort(gi[rk == kth])
+    assert tied.shape[0] == k - greater and (tied == eq[: k - greater]).all()
+
+
+def test_full_size_uniform_u32(full_u32):
+    _full_case(full_u32, "u32", (1, 1024, 131072))
+
+
+def test_full_size_normal_f32(full_f32):
+    _full_case(full_f32, "f32", (1, 1024, 131072))
+
+
+def test_full_size_adversarial():
+    x = synth.sorted_normal_f32(1 << 29, synth.DEFAULT_SEED)
+    t = dev(x)
+    full = oracle.rank_key(x, "f32")
+    for beta in (1, 2, 4, 8):
+        say("sorted 2^29 k=16384 beta", beta)
+        vals, idx, st = drt.topk_select(t, 16384, beta=beta, stats=True)
+        say("  alpha", st.alpha, "scanned", st.scanned, "candidates", st.candidates)
+        check_invariants_fast(x, full, 16384, "f32", to_np(vals), to_np(idx))
+    del t, x, full
+    h = synth.heavy_dup_u32(1 << 29, synth.DEFAULT_SEED)
+    th = dev(h)
+    fullh = oracle.rank_key(h, "u32")
+    say("heavy-dup 2^29 k=16384")
+    vals, idx, st = drt.topk_select(th, 16384, stats=True)
+    say("  alpha", st.alpha, "beta", st.beta, "scanned", st.scanned, "candidates", st.candidates)
+    check_invariants_fast(h, fullh, 16384, "u32", to_np(vals), to_np(idx))
+    # closed form: the lowest 16384 positions holding 15
+    assert (to_np(idx).view(np.uint32) == np.flatnonzero(h == 15)[:16384]).all()
