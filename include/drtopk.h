@@ -86,12 +86,15 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
  *   alpha  subrange = 2^alpha elements (Section 5.1); -1 = planner's choice
  *   beta   delegates per subrange (Rule 3): 1, 2, 4 or 8; 0 = planner's choice
  *   mode   0 = planner's choice, 1 = delegate method, 2 = plain radix select
- *          over V with no delegates */
+ *          over V with no delegates
+ *   variant  implementation of the steps after the delegate pass: 0 = one
+ *          cooperative kernel (default), 1 = one kernel per step.  Both give
+ *          bit-identical results. */
 typedef struct {
   int32_t alpha;
   int32_t beta;
   int32_t mode;
-  int32_t reserved;
+  int32_t variant;
 } drtopk_options_t;
 
 /* Counters of one call (host struct, filled after the call's work finishes;
@@ -105,6 +108,14 @@ typedef struct {
   uint64_t candidates;   /* survivors handed to the second select */
   uint32_t t_key_bits;   /* the k-th delegate (Rule 2), input bit pattern */
   uint32_t t_idx;        /* its position */
+  /* completion time of each step after the delegate pass, in ns since that
+   * part started (device clock; 0 = step not run), default variant:
+   * [0] refined threshold, [1] Rule 3 over the delegates, [2] re-read,
+   * [3] output sorted by one workgroup, [4] output buckets counted,
+   * [5] scattered, [6] bucket groups sorted, [7..12] select passes (tie
+   * fallback), [13] exact compaction, [14] fallback sort */
+  uint32_t step_ns[20];
+  uint32_t err_flags;    /* internal consistency checks that failed (0 = none) */
 } drtopk_stats_t;
 
 /* topk_select with explicit options (NULL = defaults) and optional stats. */
@@ -122,11 +133,16 @@ int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int bet
                      void* out_dkeys, uint32_t* out_didx, void* stream);
 
 /* The survivors of the filter for given alpha/beta (Rules 1-3): writes their
- * positions (unordered) to out_pos (device, capacity `cap` entries) and their
- * count to *count (host; synchronises `stream`).  DRTOPK_EINVAL if cap is too
- * small for the count. */
-int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta,
-                      uint32_t* out_pos, uint64_t cap, uint64_t* count, void* stream);
+ * positions (unordered) to out_pos (device, capacity `cap` entries), their
+ * count to *count, and the threshold the filter used to t_out (host, 2 words,
+ * nullable): its key (input bit pattern) and its position; synchronises
+ * `stream`.  Survivors are exactly the elements ranked at or above that
+ * threshold (key greater, or key equal and position not greater).  With
+ * variant 1 the threshold is the exact k-th delegate t; with variant 0 it is
+ * usually a key t' <= t read off the delegate histogram (position 0xFFFFFFFF:
+ * every element with key >= t').  DRTOPK_EINVAL if cap is too small. */
+int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta, int variant,
+                      uint32_t* out_pos, uint64_t cap, uint64_t* count, uint32_t* t_out, void* stream);
 
 /* The planner's choice for a problem (no device work). */
 int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out);

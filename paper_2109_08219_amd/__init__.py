@@ -31,14 +31,15 @@ class DrTopkError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_int32), ("beta", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("variant", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
                 ("subranges", ctypes.c_uint64), ("delegates", ctypes.c_uint64),
                 ("scanned", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
-                ("t_key_bits", ctypes.c_uint32), ("t_idx", ctypes.c_uint32)]
+                ("t_key_bits", ctypes.c_uint32), ("t_idx", ctypes.c_uint32),
+                ("step_ns", ctypes.c_uint32 * 20), ("err_flags", ctypes.c_uint32)]
 
 
 class Problem(ctypes.Structure):
@@ -65,7 +66,8 @@ def lib() -> ctypes.CDLL:
             "topk_select_batched": [ctypes.POINTER(Problem), u32, vp],
             "topk_select_ex": [vp, u64, u32, i32, vp, vp, ctypes.POINTER(Options), ctypes.POINTER(Stats), vp],
             "drtopk_delegates": [vp, u64, i32, i32, i32, vp, vp, vp],
-            "drtopk_candidates": [vp, u64, u32, i32, i32, i32, vp, u64, ctypes.POINTER(u64), vp],
+            "drtopk_candidates": [vp, u64, u32, i32, i32, i32, i32, vp, u64, ctypes.POINTER(u64),
+                                  vp, vp],
             "drtopk_plan": [u64, u32, i32, ctypes.POINTER(Options)],
             "drtopk_release_workspace": [],
             "drtopk_timing_enable": [i32],
@@ -127,14 +129,15 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _opts(alpha, beta, mode):
-    if alpha is None and beta is None and mode is None:
+def _opts(alpha, beta, mode, variant=0):
+    if alpha is None and beta is None and mode is None and not variant:
         return None
-    return Options(-1 if alpha is None else alpha, 0 if beta is None else beta, 0 if mode is None else mode, 0)
+    return Options(-1 if alpha is None else alpha, 0 if beta is None else beta, 0 if mode is None else mode,
+                   variant)
 
 
 def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, alpha=None, beta=None,
-                mode=None, stats: bool = False, stream=None):
+                mode=None, variant: int = 0, stats: bool = False, stream=None):
     """The k largest keys, sorted descending (ties: lower position first), and their positions.
 
     Returns (values, indices[, Stats]).  values has the keys' dtype; indices are int64-free uint32
@@ -145,12 +148,14 @@ def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, alpha=
         out_vals = torch.empty(k, dtype=keys.dtype, device=keys.device)
     if out_idx is None:
         out_idx = torch.empty(k, dtype=torch.int32, device=keys.device)
-    opts = _opts(alpha, beta, mode)
+    opts = _opts(alpha, beta, mode, variant)
     st = Stats() if stats else None
     rc = lib().topk_select_ex(ctypes.c_void_p(keys.data_ptr()), keys.numel(), k, code,
                               ctypes.c_void_p(out_vals.data_ptr()), ctypes.c_void_p(out_idx.data_ptr()),
                               ctypes.byref(opts) if opts is not None else None,
                               ctypes.byref(st) if st is not None else None, _stream(stream))
+    if rc != 0 and st is not None and st.err_flags:
+        raise DrTopkError(rc, f"topk_select (device check flags {st.err_flags:#x})")
     _check(rc, "topk_select")
     return (out_vals, out_idx, st) if stats else (out_vals, out_idx)
 
@@ -199,18 +204,21 @@ def delegates(keys, alpha: int, beta: int, *, dtype=None, stream=None):
     return dk.view(S, beta), di.view(S, beta)
 
 
-def candidates(keys, k: int, alpha: int, beta: int, *, dtype=None, stream=None):
-    """Positions (unordered) of the survivors of the delegate filter."""
+def candidates(keys, k: int, alpha: int, beta: int, *, variant: int = 0, dtype=None, stream=None):
+    """Positions (unordered) of the survivors of the delegate filter, and the
+    threshold (key bit pattern, position): survivors are exactly the elements
+    ranked at or above it."""
     torch = _torch()
     code = _prep(keys, dtype)
     n = keys.numel()
     cap = n
     out = torch.empty(cap, dtype=torch.int32, device=keys.device)
     cnt = ctypes.c_uint64(0)
-    rc = lib().drtopk_candidates(ctypes.c_void_p(keys.data_ptr()), n, k, code, alpha, beta,
-                                 ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(cnt), _stream(stream))
+    tout = (ctypes.c_uint32 * 2)()
+    rc = lib().drtopk_candidates(ctypes.c_void_p(keys.data_ptr()), n, k, code, alpha, beta, variant,
+                                 ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(cnt), tout, _stream(stream))
     _check(rc, "drtopk_candidates")
-    return out[: cnt.value]
+    return out[: cnt.value], (tout[0], tout[1])
 
 
 @dataclass

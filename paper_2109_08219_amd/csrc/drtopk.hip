@@ -22,6 +22,7 @@
 
 #include "drtopk.h"
 #include "kernels.h"
+#include "tail.h"
 
 namespace drtopk {
 namespace {
@@ -36,13 +37,17 @@ struct Plan {
   uint32_t k = 0;
   uint64_t S = 0, nd = 0, cap_c = 0, chunk = 0, M = 0;
   uint32_t kD = 0;   // rank sought among the delegates: min(k, |D|)
+  uint32_t slack = 0;
+  int variant = 0;   // 0: cooperative tail kernel, 1: one kernel per step
   bool all = false;  // fewer real delegates than k: no threshold, every subrange qualifies
   bool vec = false;
   size_t off_ctl = 0, off_dkey = 0, off_didx = 0, off_q = 0, off_ckey = 0, off_cidx = 0;
-  size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, total = 0;
+  size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, off_skey = 0, off_sidx = 0, total = 0;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+thread_local hipError_t tl_launch_err = hipSuccess;  // launches whose API reports errors directly
 
 int rule_alpha(uint64_t n, uint32_t k) {
   const double a = 0.5 * (std::log2((double)n) - std::log2((double)k) + kAlphaConst);
@@ -69,23 +74,31 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
   if (mode < 0 || mode > 2) return DRTOPK_EINVAL;
   if (mode == 0) mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
   p.mode = mode;
+  p.variant = opt ? opt->variant : 0;
+  if (p.variant < 0 || p.variant > 1) return DRTOPK_EINVAL;
   if (mode == 1) {
     p.beta = (opt && opt->beta > 0) ? opt->beta : default_beta(n, k);
     if (!valid_beta(p.beta)) return DRTOPK_EINVAL;
-    p.alpha = (opt && opt->alpha >= 0) ? opt->alpha : rule_alpha(n, k);
+    p.alpha = (opt && opt->alpha >= 0) ? opt->alpha : rule_alpha(n, k) + (p.beta >= 2 ? 2 : 0);
+    if (p.alpha > 24) p.alpha = 24;
     if (p.alpha > 24) return DRTOPK_EINVAL;
     const uint64_t L = 1ull << p.alpha;
     p.S = (n + L - 1) >> p.alpha;
     p.nd = p.S * (uint64_t)p.beta;
+    if (p.nd >= (1ull << 32)) return DRTOPK_EINVAL;  // delegate vector must be indexable by 32 bits
     const uint64_t full = n >> p.alpha, last = n & (L - 1);
     const uint64_t per_full = L < (uint64_t)p.beta ? L : (uint64_t)p.beta;
     const uint64_t nd_valid = full * per_full + (last < (uint64_t)p.beta ? last : (uint64_t)p.beta);
     p.kD = p.nd < (uint64_t)k ? (uint32_t)p.nd : k;
+    // survivors: at most floor(m/beta)*L + m when m delegates rank at or above
+    // the threshold; the tail keeps m <= kD + slack (exact threshold otherwise)
+    p.slack = p.kD / 8 > 64 ? p.kD / 8 : 64;
     if (nd_valid < k) {
       p.cap_c = n;
       p.all = true;
     } else {
-      const uint64_t c = (uint64_t)((k - 1) / p.beta) * L + k;
+      const uint64_t m = (uint64_t)p.kD + p.slack;
+      const uint64_t c = (m / p.beta) * L + m;
       p.cap_c = c < n ? c : n;
     }
     p.chunk = (1ull << 18) > 4 * L ? (1ull << 18) : 4 * L;
@@ -108,6 +121,10 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
     p.off_q = seg(p.S * 4);
     p.off_ckey = seg(p.cap_c * 4);
     p.off_cidx = seg(p.cap_c * 4);
+    if (p.variant == 0) {
+      p.off_skey = seg(p.cap_c * 4);  // survivors scattered into output-bucket order
+      p.off_sidx = seg(p.cap_c * 4);
+    }
   }
   p.off_okey = seg((size_t)k * 4);
   p.off_oidx = seg((size_t)k * 4);
@@ -245,9 +262,38 @@ struct Runner {
     }
   }
 
+  template <int B, bool V>
+  static void launch_tail_t(TailArgs& ta, hipStream_t st) {
+    static int blocks = 0;  // blocks that fit the device at once (phases need no co-residency)
+    if (blocks == 0) {
+      int dev = 0, cus = 0, per = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_tail<DT, B, V>),
+                                                          kTailThreads, 0);
+      if (per > 2) per = 2;
+      if (per < 1) per = 1;
+      blocks = cus * per;
+    }
+    hipLaunchKernelGGL((k_tail<DT, B, V>), dim3(blocks), dim3(kTailThreads), 0, st, ta);
+  }
+
+  static void launch_tail(const Plan& p, TailArgs& ta, hipStream_t st) {
+    switch (p.beta * 2 + (p.vec ? 1 : 0)) {
+      case 2: launch_tail_t<1, false>(ta, st); break;
+      case 3: launch_tail_t<1, true>(ta, st); break;
+      case 4: launch_tail_t<2, false>(ta, st); break;
+      case 5: launch_tail_t<2, true>(ta, st); break;
+      case 8: launch_tail_t<4, false>(ta, st); break;
+      case 9: launch_tail_t<4, true>(ta, st); break;
+      case 16: launch_tail_t<8, false>(ta, st); break;
+      default: launch_tail_t<8, true>(ta, st); break;
+    }
+  }
+
   static void qualify(const Plan& p, uint32_t* dkey, uint32_t* didx, Ctl* ctl, uint32_t* Q, uint32_t* ckey,
                       uint32_t* cidx, hipStream_t st) {
-    const unsigned g = grid_for(p.S, 256, 8192);
+    const unsigned g = grid_for(p.S, 256 * 16, 1024);
     switch (p.beta) {
       case 1: hipLaunchKernelGGL((k_qualify<1>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
       case 2: hipLaunchKernelGGL((k_qualify<2>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
@@ -257,16 +303,17 @@ struct Runner {
   }
 
   // The k sorted outputs from okey/oidx (exactly k entries), k > kSmallCap.
+  // gated: 0 always run, 1 only if the tail kernel set ctl->need_merge
   static void big_sort(const Plan& p, void* ws, uint32_t* out_vals, uint32_t* out_idx, uint32_t* out_kth,
-                       hipStream_t st) {
+                       int gated, Ctl* ctl, hipStream_t st) {
     uint64_t* A = at<uint64_t>(ws, p.off_A);
     uint64_t* B = at<uint64_t>(ws, p.off_B);
     hipLaunchKernelGGL(k_blocksort, dim3((unsigned)(p.M / kSortTile)), dim3(1024), 0, st,
-                       at<uint32_t>(ws, p.off_okey), at<uint32_t>(ws, p.off_oidx), p.k, A);
+                       at<uint32_t>(ws, p.off_okey), at<uint32_t>(ws, p.off_oidx), p.k, A, gated, ctl);
     for (uint64_t run = kSortTile; run < p.M; run <<= 1) {
       const int last = (2 * run == p.M) ? 1 : 0;
       hipLaunchKernelGGL((k_merge<DT>), dim3((unsigned)(p.M / 256)), dim3(256), 0, st, A, B, p.M, run, last, p.k,
-                         out_vals, out_idx, out_kth);
+                         out_vals, out_idx, out_kth, gated, ctl);
       std::swap(A, B);
     }
   }
@@ -289,6 +336,43 @@ struct Runner {
     uint32_t* okey = at<uint32_t>(ws, p.off_okey);
     uint32_t* oidx = at<uint32_t>(ws, p.off_oidx);
     const uint32_t k = p.k;
+    if (p.mode == 1 && p.variant == 0) {
+      uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
+      uint32_t* didx = at<uint32_t>(ws, p.off_didx);
+      delegate(p, keys, dkey, didx, ctl, st);
+      pm.mid(st);
+      TailArgs ta;
+      ta.keys = keys;
+      ta.n = p.n;
+      ta.alpha = p.alpha;
+      ta.S = p.S;
+      ta.nd = p.nd;
+      ta.k = k;
+      ta.kD = p.kD;
+      ta.slack = p.slack;
+      ta.all = p.all ? 1 : 0;
+      ta.kth_only = kth_only ? 1 : 0;
+      ta.stop_after_scan = filter_only ? 1 : 0;
+      ta.big_sort = (!kth_only && k > (uint32_t)kSmallCap) ? 1 : 0;
+      ta.dkey = dkey;
+      ta.didx = didx;
+      ta.Q = at<uint32_t>(ws, p.off_q);
+      ta.ckey = at<uint32_t>(ws, p.off_ckey);
+      ta.cidx = at<uint32_t>(ws, p.off_cidx);
+      ta.skey = at<uint32_t>(ws, p.off_skey);
+      ta.sidx = at<uint32_t>(ws, p.off_sidx);
+      ta.okey = okey;
+      ta.oidx = oidx;
+      ta.cap_s = (uint32_t)p.cap_c;
+      ta.out_vals = out_vals;
+      ta.out_idx = out_idx;
+      ta.out_kth = out_kth;
+      ta.ctl = ctl;
+      launch_tail(p, ta, st);
+      // the merge sort runs only if the tail fell back to its select path
+      if (ta.big_sort && !filter_only) big_sort(p, ws, out_vals, out_idx, out_kth, 1, ctl, st);
+      return;
+    }
     if (p.mode == 1) {
       uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
       uint32_t* didx = at<uint32_t>(ws, p.off_didx);
@@ -301,7 +385,8 @@ struct Runner {
       for (int pass = 1; pass < kPasses; ++pass)
         hipLaunchKernelGGL((k_pass<SRC_D, DT>), dim3(gD), dim3(256), 0, st, dkey, didx, p.nd, pass, 0, ctl, p.kD);
       qualify(p, dkey, didx, ctl, Q, ckey, cidx, st);
-      const unsigned gS = grid_for((uint64_t)((k - 1) / p.beta) + 1, 4, 2048);
+      // expected concatenated length: about k/beta subranges of 2^alpha (grid-stride covers more)
+      const unsigned gS = grid_for(((uint64_t)((k - 1) / p.beta) + 1) << p.alpha, 4096, 2048);
       if (p.vec)
         hipLaunchKernelGGL((k_scan<DT, true>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
       else
@@ -324,7 +409,7 @@ struct Runner {
         hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 2, k,
                            ctl, out_vals, out_idx, out_kth);
       else
-        big_sort(p, ws, out_vals, out_idx, out_kth, st);
+        big_sort(p, ws, out_vals, out_idx, out_kth, 0, ctl, st);
     } else {
       if (p.n <= (uint64_t)kSmallCap) {
         hipLaunchKernelGGL((k_final_small<SRC_V, DT>), dim3(1), dim3(1024), 0, st, keys, (const uint32_t*)nullptr,
@@ -347,7 +432,7 @@ struct Runner {
         hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 0, k,
                            ctl, out_vals, out_idx, out_kth);
       else
-        big_sort(p, ws, out_vals, out_idx, out_kth, st);
+        big_sort(p, ws, out_vals, out_idx, out_kth, 0, ctl, st);
     }
   }
 };
@@ -394,7 +479,9 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
   else
     Runner<DT_U32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
                         kth_only, filter_only, s);
-  if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+  const hipError_t le = tl_launch_err;
+  tl_launch_err = hipSuccess;
+  if (hipGetLastError() != hipSuccess || le != hipSuccess) return DRTOPK_EDEVICE;
   return after(p, ws->ptr, s);
 }
 
@@ -413,6 +500,10 @@ int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   stats->candidates = p.mode == 1 ? h.nc : p.n;
   stats->t_key_bits = p.mode == 1 ? host_dec(p.dt, (uint32_t)(h.selD.prefix >> 32)) : 0;
   stats->t_idx = p.mode == 1 ? ~(uint32_t)h.selD.prefix : 0;
+  const uint64_t t0 = h.tstamp[kPhases + 1];
+  for (int i = 0; i < kPhases && i < 20; ++i)
+    stats->step_ns[i] = (t0 && h.tstamp[i] >= t0) ? (uint32_t)((h.tstamp[i] - t0) * 10) : 0;
+  stats->err_flags = h.err;
   if (h.err) return DRTOPK_EDEVICE;
   return DRTOPK_OK;
 }
@@ -509,11 +600,11 @@ int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int bet
   return DRTOPK_OK;
 }
 
-int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta, uint32_t* out_pos,
-                      uint64_t cap, uint64_t* count, void* stream) {
+int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int alpha, int beta, int variant,
+                      uint32_t* out_pos, uint64_t cap, uint64_t* count, uint32_t* t_out, void* stream) {
   if (!out_pos || !count) return DRTOPK_EINVAL;
   if (alpha < 0 || alpha > 24 || !valid_beta(beta)) return DRTOPK_EINVAL;
-  drtopk_options_t o{alpha, beta, 1, 0};
+  drtopk_options_t o{alpha, beta, 1, variant};
   try {
     return run_common(keys, n, k, dtype, nullptr, nullptr, nullptr, true, &o, stream,
                       [&](const Plan& p, void* ws, hipStream_t s) {
@@ -521,6 +612,14 @@ int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int a
                         uint32_t nc = 0;
                         if (hipMemcpy(&nc, &at<Ctl>(ws, p.off_ctl)->nc, 4, hipMemcpyDeviceToHost) != hipSuccess)
                           return (int)DRTOPK_EDEVICE;
+                        if (t_out) {
+                          uint64_t t = 0;
+                          if (hipMemcpy(&t, &at<Ctl>(ws, p.off_ctl)->selD.prefix, 8, hipMemcpyDeviceToHost) !=
+                              hipSuccess)
+                            return (int)DRTOPK_EDEVICE;
+                          t_out[0] = host_dec(p.dt, (uint32_t)(t >> 32));
+                          t_out[1] = ~(uint32_t)t;
+                        }
                         *count = nc;
                         if (nc > cap) return (int)DRTOPK_EINVAL;
                         if (nc && hipMemcpy(out_pos, at<uint32_t>(ws, p.off_cidx), (size_t)nc * 4,
@@ -545,7 +644,7 @@ int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out) {
   out->alpha = p.alpha;
   out->beta = p.beta;
   out->mode = p.mode;
-  out->reserved = 0;
+  out->variant = p.variant;
   return DRTOPK_OK;
 }
 

@@ -36,14 +36,49 @@ struct Sel {
   uint32_t found;   // 1 once the bucket search succeeded, 0 on an inconsistency
 };
 
+// One phase of the tail kernel: chunk claims, completed chunks, ready flag
+// (each on its own 256-byte line).
+struct Phase {
+  uint32_t claim;
+  uint32_t pad0[31];
+  uint32_t done;
+  uint32_t pad1[31];
+  uint32_t ready;
+  uint32_t pad2[63];
+};
+constexpr int kPhases = 24;
+
 // Per-call control block at the head of the workspace; zeroed by k_init.
 struct Ctl {
+  Phase ph[kPhases];
   uint32_t histD[kPasses][kBins];  // digit histograms of the delegate select
   uint32_t histC[kPasses][kBins];  // digit histograms of the survivor select
+  uint32_t histL[kBins];           // delegates by log-distance from the top of the key range
+  uint32_t histW[kPasses][kBins];  // digit histograms of the select over W (compacted delegates)
+  uint32_t histH[kBins];           // refinement of the cut bin (next finer digit)
+  uint32_t bcount[kBins];          // survivors per output bucket
+  uint32_t bcur[kBins];            // scatter cursors per output bucket
   Sel selD;                        // k-th largest delegate (the threshold t)
   Sel selC;                        // k-th largest survivor
   uint32_t ticketD[kPasses + 1];
   uint32_t ticketC[kPasses + 1];
+  Sel selW;
+  uint32_t cut_lo, cut_hi;  // key interval of the cut bin
+  uint32_t cut_rank;        // rank of the kD-th delegate inside the cut bin
+  uint32_t cut_count;       // delegates in the cut bin
+  uint64_t cmax;            // largest survivor composite
+  uint64_t ncmin;           // complement of the smallest survivor composite (so zero is neutral)
+  uint32_t bigbucket;       // an output bucket overflows one workgroup: take the select path
+  uint32_t ngroups;         // output sort groups
+  uint32_t need_merge;      // the large-k merge-sort kernels must run (select fallback taken)
+  uint32_t wmap;  // monotone map used to cut the delegates: 0 top 11 bits, 1 log-distance
+  uint32_t wbin;  // delegates with bin >= wbin form W, a superset of those ranked >= t
+  uint32_t wsize; // |W|, known from the fused histogram
+  uint32_t nw;    // W fill level
+  uint32_t selpub[8];  // selection state published between tail phases (W: 0..3, survivors: 4..7)
+  uint32_t uniq_idx;  // position of a unique entry found by a tail pass
+  uint32_t tpub[2];   // threshold t published by block 0 of the tail (coherent stores)
+  uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
   uint32_t nq;    // subranges to re-read
   uint32_t nc;    // survivors
   uint32_t nout;  // compacted outputs (large-survivor path)
@@ -51,6 +86,8 @@ struct Ctl {
   uint32_t cap_q; // capacity of the qualifying-subrange list
   uint32_t cap_c; // capacity of the survivor buffer
   uint32_t all;   // 1: fewer delegates than k, every subrange qualifies (t = lowest)
+  uint32_t boff[kBins + 1];   // first output slot of each bucket
+  uint32_t gfirst[kBins + 1]; // first bucket of each sort group
 };
 
 // Fill levels clamped to their buffers (a violated bound sets err instead of
@@ -77,6 +114,55 @@ __device__ __forceinline__ uint32_t comp_key(uint64_t c) { return (uint32_t)(c >
 __device__ __forceinline__ uint32_t comp_pos(uint64_t c) { return ~(uint32_t)c; }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+// Monotone bin of a key by its distance from the top of the uint32 range,
+// with 64 sub-bins per octave: maxima of many keys crowd near the top, where
+// equal-width digits put most of them in one bin.  Larger key -> larger or
+// equal bin; bins 320..2047 are used.
+__device__ __forceinline__ uint32_t log_bin(uint32_t key) {
+  const uint32_t x = ~key;
+  if (x < 64u) return 2047u - x;
+  const uint32_t e = 32u - (uint32_t)__clz((int)x);  // bit length, 7..32
+  const uint32_t m = (x >> (e - 7u)) & 63u;
+  return 2047u - (64u + (e - 7u) * 64u + m);
+}
+__device__ __forceinline__ uint32_t top_bin(uint32_t key) { return key >> 21; }
+
+// Key interval [lo, hi] of a bin of either map (inverse of top_bin / log_bin).
+__device__ __forceinline__ void bin_interval(uint32_t map, uint32_t bin, uint32_t& lo, uint32_t& hi) {
+  if (map == 0) {
+    lo = bin << 21;
+    hi = lo | 0x1FFFFFu;
+    return;
+  }
+  const uint32_t f = 2047u - bin;
+  if (f < 64u) {
+    lo = hi = ~f;
+    return;
+  }
+  const uint32_t e = 7u + (f - 64u) / 64u, m = (f - 64u) % 64u;
+  const uint64_t xlo = (uint64_t)(64u + m) << (e - 7u);
+  const uint64_t xhi = ((uint64_t)(65u + m) << (e - 7u)) - 1u;
+  lo = ~(uint32_t)xhi;
+  hi = ~(uint32_t)xlo;
+}
+
+__device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32u - (uint32_t)__clz((int)x) : 0u; }
+__device__ __forceinline__ uint32_t bitlen64(uint64_t x) {
+  return x ? 64u - (uint32_t)__clzll((long long)x) : 0u;
+}
+
+// Coherent (device-scope, sc1) accesses for data exchanged between blocks of
+// one kernel: they bypass the per-XCD L2, so no cache writeback is needed.
+__device__ __forceinline__ void st_coh(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

@@ -115,14 +115,19 @@ __device__ inline void flush_hist(const uint32_t* lh, uint32_t* gh) {
 
 // Completes digit pass p: the last block to finish (ticket) derives the new
 // selection state from the finished global histogram.
+//
+// Only atomics carry data between blocks here, so no cache writeback is
+// needed: each wave waits until its own histogram atomics have completed
+// (s_waitcnt; an agent-scope fence would instead write back the whole L2 of
+// the XCD, once per wave), the block then takes a ticket, and the last block
+// reads the histogram with coherent (sc1) atomic loads.
 __device__ inline void finish_pass(uint32_t* gh, uint32_t* ticket, Sel* sel, int p, uint32_t k,
                                    Ctl* ctl, uint32_t* s_scan, uint32_t* s_out, int* s_last) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) *s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
   __syncthreads();
   if (!*s_last) return;
-  __threadfence();
   uint64_t prefix = 0, mask = 0;
   uint32_t rank = k;
   if (p > 0) {
@@ -143,6 +148,65 @@ __device__ inline void finish_pass(uint32_t* gh, uint32_t* ticket, Sel* sel, int
 }
 
 // ---------------------------------------------------------------------------
+// LDS-staged appends: waves append into a block buffer with LDS atomics; the
+// block reserves global space with one atomic per flush.
+
+template <int CAP>
+struct Stage {
+  uint32_t key[CAP];
+  uint32_t idx[CAP];
+  uint32_t n;
+  uint32_t base;
+};
+
+template <int CAP>
+__device__ __forceinline__ void stage_init(Stage<CAP>& S) {
+  if (threadIdx.x == 0) S.n = 0;
+  __syncthreads();
+}
+
+// Whole wave active.  Lanes with `pred` append (key, idx).
+template <int CAP>
+__device__ __forceinline__ void stage_push(Stage<CAP>& S, bool pred, uint32_t key, uint32_t idx) {
+  const uint64_t b = __ballot(pred);
+  if (!b) return;
+  const int leader = __ffsll((unsigned long long)b) - 1;
+  uint32_t off = 0;
+  if ((int)lane_id() == leader) off = atomicAdd(&S.n, (uint32_t)__popcll(b));
+  off = (uint32_t)__shfl((int)off, leader) + mbcnt(b);
+  if (pred) {
+    S.key[off] = key;
+    S.idx[off] = idx;
+  }
+}
+
+// Block-uniform.  Flushes when `force` or when fewer than `margin` slots are
+// left.  gidx may be null (keys only).  Entries past gcap set ctl->err.
+template <int CAP>
+__device__ __forceinline__ void stage_flush(Stage<CAP>& S, uint32_t* gcount, uint32_t gcap, uint32_t* gkey,
+                                            uint32_t* gidx, Ctl* ctl, bool force, uint32_t margin) {
+  __syncthreads();
+  const uint32_t n = S.n;
+  const bool doit = n != 0 && (force || n + margin > (uint32_t)CAP);
+  __syncthreads();  // every wave has read n before anyone appends again
+  if (!doit) return;
+  if (threadIdx.x == 0) S.base = atomicAdd(gcount, n);
+  __syncthreads();
+  const uint32_t base = S.base;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (base + i < gcap) {
+      gkey[base + i] = S.key[i];
+      if (gidx) gidx[base + i] = S.idx[i];
+    } else {
+      ctl->err |= 16u;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.n = 0;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // delegate vector
 
 template <int BETA>
@@ -153,7 +217,51 @@ __device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb,
     const uint32_t kk = comp_key(tb.c[j]);
     dkey[s * BETA + j] = kk;
     didx[s * BETA + j] = comp_pos(tb.c[j]);  // padding (composite 0) gives 0xFFFFFFFF
-    atomicAdd(&lh[kk >> 21], 1u);
+    atomicAdd(&lh[top_bin(kk)], 1u);
+    atomicAdd(&lh[kBins + log_bin(kk)], 1u);
+  }
+}
+
+// End of the delegate pass: the last block finds, under both monotone maps,
+// the bin holding the kD-th largest delegate, and keeps the map whose cut
+// leaves the smaller set W (all delegates in that bin or above).
+__device__ inline void finish_delegates(const uint32_t* lh, Ctl* ctl, uint32_t kD, uint32_t* s_scan,
+                                        uint32_t* s_out, int* s_last) {
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
+    const uint32_t a = lh[i], b = lh[kBins + i];
+    if (a) atomicAdd(&ctl->histD[0][i], a);
+    if (b) atomicAdd(&ctl->histL[i], b);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) *s_last = (atomicAdd(&ctl->ticketD[0], 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!*s_last) return;
+  block_select_bucket(ctl->histD[0], kD, s_scan, s_out);
+  const uint32_t b0 = s_out[0], r0 = s_out[1], f0 = s_out[2];
+  const uint32_t c0 = f0 ? atomic_load_u32(&ctl->histD[0][b0]) : 0xFFFFFFFFu;
+  __syncthreads();
+  block_select_bucket(ctl->histL, kD, s_scan, s_out);
+  const uint32_t b1 = s_out[0], r1 = s_out[1], f1 = s_out[2];
+  const uint32_t c1 = f1 ? atomic_load_u32(&ctl->histL[b1]) : 0xFFFFFFFFu;
+  if (threadIdx.x == 0) {
+    const uint64_t w0 = (uint64_t)(kD - r0) + c0, w1 = (uint64_t)(kD - r1) + c1;
+    if (!f0 && !f1) ctl->err |= 1u;
+    const bool use_log = f1 && (!f0 || w1 < w0);
+    ctl->wmap = use_log ? 1u : 0u;
+    ctl->wbin = use_log ? b1 : b0;
+    ctl->wsize = (uint32_t)(use_log ? w1 : w0);
+    uint32_t lo = 0, hi = 0;
+    bin_interval(ctl->wmap, ctl->wbin, lo, hi);
+    ctl->cut_lo = lo;
+    ctl->cut_hi = hi;
+    ctl->cut_rank = use_log ? r1 : r0;
+    ctl->cut_count = (uint32_t)(use_log ? c1 : c0);
+    // kept for the multi-pass delegate select (plain-radix fallback path)
+    ctl->selD.prefix = (uint64_t)b0 << pass_shift(0);
+    ctl->selD.mask = 0x7FFull << pass_shift(0);
+    ctl->selD.rank = r0;
+    ctl->selD.found = f0;
   }
 }
 
@@ -257,11 +365,11 @@ template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                   uint64_t chunk, uint32_t* __restrict__ dkey,
                                                   uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
-  __shared__ uint32_t lh[kBins];
+  __shared__ uint32_t lh[2 * kBins];
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
-  for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+  for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
   __syncthreads();
   const uint32_t wave = threadIdx.x >> 6;
   const uint64_t wlen = chunk >> 2;
@@ -273,8 +381,7 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
     else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh);
   }
   __syncthreads();
-  flush_hist(lh, ctl->histD[0]);
-  finish_pass(ctl->histD[0], &ctl->ticketD[0], &ctl->selD, 0, k, ctl, s_scan, s_out, &s_last);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last);
 }
 
 // Subranges of 1 or 2 elements, or any alpha when the planner asks for the
@@ -283,11 +390,11 @@ template <int DT, int BETA>
 __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restrict__ keys, uint64_t n,
                                                          int alpha, uint64_t S, uint32_t* __restrict__ dkey,
                                                          uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
-  __shared__ uint32_t lh[kBins];
+  __shared__ uint32_t lh[2 * kBins];
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
-  for (int i = threadIdx.x; i < kBins; i += 256) lh[i] = 0;
+  for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
   __syncthreads();
   for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < S; s += (uint64_t)gridDim.x * 256) {
     TopB<BETA> tb;
@@ -298,8 +405,7 @@ __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restr
     emit_delegates<BETA>(s, tb, dkey, didx, lh);
   }
   __syncthreads();
-  flush_hist(lh, ctl->histD[0]);
-  finish_pass(ctl->histD[0], &ctl->ticketD[0], &ctl->selD, 0, k, ctl, s_scan, s_out, &s_last);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,6 +474,10 @@ template <int BETA>
 __global__ __launch_bounds__(256) void k_qualify(const uint32_t* __restrict__ dkey, const uint32_t* __restrict__ didx,
                                                  uint64_t S, Ctl* ctl, uint32_t* __restrict__ Q,
                                                  uint32_t* __restrict__ ckey, uint32_t* __restrict__ cidx) {
+  __shared__ Stage<1024> sq;
+  __shared__ Stage<4096> sc;
+  stage_init(sq);
+  stage_init(sc);
   const uint64_t t = ctl->all ? 0ull : ctl->selD.prefix;
   const uint32_t cap_q = ctl->cap_q, cap_c = ctl->cap_c;
   for (uint64_t s0 = (uint64_t)blockIdx.x * 256; s0 < S; s0 += (uint64_t)gridDim.x * 256) {
@@ -376,60 +486,69 @@ __global__ __launch_bounds__(256) void k_qualify(const uint32_t* __restrict__ dk
     uint64_t dc = 0;
     if (ok) dc = comp(dkey[s * BETA + BETA - 1], didx[s * BETA + BETA - 1]);
     const bool scan = ok && dc > t;
-    const uint32_t slot = wave_append(scan, &ctl->nq);
-    if (scan) {
-      if (slot < cap_q) Q[slot] = (uint32_t)s;
-      else ctl->err |= 8u;
-    }
+    stage_push(sq, scan, (uint32_t)s, 0u);
 #pragma unroll
     for (int j = 0; j < BETA; ++j) {
       uint64_t c = 0;
       if (ok && !scan) c = comp(dkey[s * BETA + j], didx[s * BETA + j]);
       const bool take = c != 0 && c >= t;
-      const uint32_t sl = wave_append(take, &ctl->nc);
-      if (take) {
-        if (sl < cap_c) { ckey[sl] = comp_key(c); cidx[sl] = comp_pos(c); }
-        else ctl->err |= 16u;
-      }
+      stage_push(sc, take, comp_key(c), comp_pos(c));
     }
+    stage_flush(sq, &ctl->nq, cap_q, Q, nullptr, ctl, false, 256);
+    stage_flush(sc, &ctl->nc, cap_c, ckey, cidx, ctl, false, 256 * BETA);
   }
+  stage_flush(sq, &ctl->nq, cap_q, Q, nullptr, ctl, true, 0);
+  stage_flush(sc, &ctl->nc, cap_c, ckey, cidx, ctl, true, 0);
 }
 
-// Re-read the qualifying subranges (one wave each) and keep every element
-// ranked at or above t (Rule 2's filter, inclusive).
+// The paper's concatenated vector, never materialised: element e of the
+// concatenation of the qualifying subranges is position
+// Q[e >> alpha] * 2^alpha + (e & (2^alpha - 1)).  Each thread takes 4
+// consecutive elements (one 128-bit load when alpha >= 2), so work is spread
+// evenly whatever the subrange size; elements ranked at or above t survive
+// (Rule 2's filter, inclusive).
 template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void k_scan(const uint32_t* __restrict__ keys, uint64_t n, int alpha, Ctl* ctl,
                                               const uint32_t* __restrict__ Q, uint32_t* __restrict__ ckey,
                                               uint32_t* __restrict__ cidx) {
-  const uint32_t nq = clamp_nq(ctl);
+  __shared__ Stage<4096> sc;
+  stage_init(sc);
+  const uint64_t total = (uint64_t)clamp_nq(ctl) << alpha;
   const uint32_t cap_c = ctl->cap_c;
   const uint64_t t = ctl->all ? 0ull : ctl->selD.prefix;
-  const uint32_t lane = lane_id();
-  const uint32_t nw = gridDim.x * 4;
-  for (uint32_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < nq; q += nw) {
-    const uint64_t lo = (uint64_t)Q[q] << alpha;
-    const uint64_t hi = lo + (1ull << alpha) < n ? lo + (1ull << alpha) : n;
-    for (uint64_t b = lo; b < hi; b += 256) {
-      const uint64_t p = b + lane * 4;
-      uint32_t v[4];
-      if (VEC && alpha >= 2 && p + 4 <= hi) {
+  const uint64_t lmask = (1ull << alpha) - 1;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * 1024; e0 < total; e0 += (uint64_t)gridDim.x * 1024) {
+    const uint64_t e = e0 + threadIdx.x * 4;
+    uint32_t v[4];
+    uint64_t pos[4];
+    bool in[4];
+    if (VEC && alpha >= 2) {
+      const uint64_t p = e < total ? ((uint64_t)Q[e >> alpha] << alpha) + (e & lmask) : n;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { pos[c] = p + c; in[c] = p + c < n; }
+      if (p + 4 <= n) {
         load4<DT, true>(keys, p, v);
       } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = p + c < hi ? keys[p + c] : 0u;
+        for (int c = 0; c < 4; ++c) v[c] = in[c] ? keys[p + c] : 0u;
       }
+    } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const uint64_t cc = comp(enc<DT>(v[c]), (uint32_t)(p + c));
-        const bool take = (p + c < hi) && cc >= t;
-        const uint32_t sl = wave_append(take, &ctl->nc);
-        if (take) {
-          if (sl < cap_c) { ckey[sl] = comp_key(cc); cidx[sl] = (uint32_t)(p + c); }
-          else ctl->err |= 16u;
-        }
+        const uint64_t ec = e + c;
+        pos[c] = ec < total ? ((uint64_t)Q[ec >> alpha] << alpha) + (ec & lmask) : n;
+        in[c] = pos[c] < n;
+        v[c] = in[c] ? keys[pos[c]] : 0u;
       }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t cc = comp(enc<DT>(v[c]), (uint32_t)pos[c]);
+      stage_push(sc, in[c] && cc >= t, comp_key(cc), (uint32_t)pos[c]);
+    }
+    stage_flush(sc, &ctl->nc, cap_c, ckey, cidx, ctl, false, 1024);
   }
+  stage_flush(sc, &ctl->nc, cap_c, ckey, cidx, ctl, true, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,20 +605,22 @@ template <int SRC, int DT>
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ key, const uint32_t* __restrict__ idx,
                                                  uint64_t count_static, int gate, uint32_t k, Ctl* ctl,
                                                  uint32_t* __restrict__ okey, uint32_t* __restrict__ oidx) {
+  __shared__ Stage<2048> so;
   if (gated_off(ctl, gate)) return;
+  stage_init(so);
   const uint64_t count = (SRC == SRC_C) ? (uint64_t)clamp_nc(ctl) : count_static;
   const uint64_t T = ctl->selC.prefix;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < count; i0 += (uint64_t)gridDim.x * 256) {
-    const uint64_t i = i0 + threadIdx.x;
-    uint64_t c = 0;
-    if (i < count) c = src_comp<SRC, DT>(key, idx, i);
-    const bool take = i < count && c >= T;
-    const uint32_t sl = wave_append(take, &ctl->nout);
-    if (take) {
-      if (sl < k) { okey[sl] = comp_key(c); oidx[sl] = comp_pos(c); }
-      else ctl->err |= 4u;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 1024; i0 < count; i0 += (uint64_t)gridDim.x * 1024) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t i = i0 + c * 256 + threadIdx.x;
+      uint64_t x = 0;
+      if (i < count) x = src_comp<SRC, DT>(key, idx, i);
+      stage_push(so, i < count && x >= T, comp_key(x), comp_pos(x));
     }
+    stage_flush(so, &ctl->nout, k, okey, oidx, ctl, false, 1024);
   }
+  stage_flush(so, &ctl->nout, k, okey, oidx, ctl, true, 0);
 }
 
 // k-th value straight from the survivor select (k-selection needs no sort).
@@ -512,8 +633,9 @@ __global__ void k_kth_from_sel(int gate, Ctl* ctl, uint32_t* out_kth) {
 // Sort tiles of kSortTile composites in LDS (descending); pads are 0.
 __global__ __launch_bounds__(1024) void k_blocksort(const uint32_t* __restrict__ okey,
                                                     const uint32_t* __restrict__ oidx, uint32_t k,
-                                                    uint64_t* __restrict__ A) {
+                                                    uint64_t* __restrict__ A, int gated, const Ctl* ctl) {
   __shared__ uint64_t buf[kSortTile];
+  if (gated && !ctl->need_merge) return;
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
   for (uint32_t j = threadIdx.x; j < kSortTile; j += 1024) {
     const uint64_t i = base + j;
@@ -542,7 +664,8 @@ __global__ __launch_bounds__(1024) void k_blocksort(const uint32_t* __restrict__
 template <int DT>
 __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ A, uint64_t* __restrict__ B, uint64_t M,
                                                uint64_t run, int last, uint32_t k, uint32_t* out_vals,
-                                               uint32_t* out_idx, uint32_t* out_kth) {
+                                               uint32_t* out_idx, uint32_t* out_kth, int gated, const Ctl* ctl) {
+  if (gated && !ctl->need_merge) return;
   const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
   const uint64_t pair = i / (2 * run) * (2 * run);

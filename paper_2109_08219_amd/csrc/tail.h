@@ -1,0 +1,772 @@
+// Everything after the delegate pass, in one launch.
+//
+// Phases:
+//   W   compact the delegates at or above the cut found by the delegate pass
+//       (a superset of those ranked >= t, Rule 2's threshold);
+//   T   t = the kD-th largest of W: one block sorts W in LDS when W is small,
+//       else a multi-block MSD radix select (one phase per digit) followed by
+//       Rule 3 over W;
+//   S   re-read the qualifying subranges as one virtual concatenated vector,
+//       keeping elements ranked >= t;
+//   F   the k-th survivor and the output: one block sorts the survivors in
+//       LDS when they are few, else radix select + exact compaction (the sort
+//       of a large k follows as separate kernels).
+// Work inside a phase is claimed chunk by chunk from an atomic counter; a
+// phase is complete when the chunks claimed have been reported done, and the
+// block that reports the last chunk finalises it and raises the phase's ready
+// flag.  A waiting block therefore only ever waits for chunks that running
+// blocks hold, so the kernel needs no co-residency guarantee (plain launch,
+// safe beside kernels on other streams).  Waits are bounded and flag
+// ctl->err if exceeded.  Data crossing blocks goes through atomics and
+// coherent (sc1) stores/loads only.
+#pragma once
+
+#include "kernels.h"
+
+namespace drtopk {
+
+constexpr int kTailThreads = 512;
+constexpr uint32_t kSpinLimit = 1u << 20;  // ~1 s of polling, then give up and flag
+
+struct TailArgs {
+  const uint32_t* keys;
+  uint64_t n;
+  int alpha;
+  uint64_t S;
+  uint64_t nd;
+  uint32_t k, kD;
+  uint32_t slack;  // survivor buffers hold floor((kD+slack)/beta)*2^alpha + kD + slack entries
+  int all, kth_only, stop_after_scan, big_sort;
+  const uint32_t* dkey;
+  const uint32_t* didx;
+  uint32_t *Q, *ckey, *cidx, *skey, *sidx, *okey, *oidx;
+  uint32_t cap_s;
+  uint32_t *out_vals, *out_idx, *out_kth;
+  Ctl* ctl;
+};
+
+// Bin holding the rank-th largest in a 2048-bin global histogram (coherent
+// loads), blockDim.x == kTailThreads: s_out = {bin, rank in bin, found, count}.
+__device__ inline void tail_bucket(const uint32_t* gh, uint32_t rank, uint32_t* s_scan, uint32_t* s_out) {
+  constexpr int PER = kBins / kTailThreads;  // 4
+  const int t = threadIdx.x;
+  uint32_t c[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    c[j] = ld_coh(&gh[kBins - 1 - PER * t - j]);
+    sum += c[j];
+  }
+  s_scan[t] = sum;
+  if (t == 0) { s_out[0] = 0; s_out[1] = 0; s_out[2] = 0; s_out[3] = 0; }
+  __syncthreads();
+  for (int off = 1; off < kTailThreads; off <<= 1) {
+    const uint32_t x = t >= off ? s_scan[t - off] : 0u;
+    __syncthreads();
+    s_scan[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = s_scan[t], excl = incl - sum;
+  if (excl < rank && rank <= incl) {
+    uint32_t cum = excl;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (cum + c[j] >= rank) {
+        s_out[0] = kBins - 1 - PER * t - j;
+        s_out[1] = rank - cum;
+        s_out[2] = 1;
+        s_out[3] = c[j];
+        break;
+      }
+      cum += c[j];
+    }
+  }
+  __syncthreads();
+}
+
+// LDS bitonic sort, descending, of P (power of two) composites.
+__device__ inline void lds_sort_desc(uint64_t* buf, uint32_t P) {
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
+        const uint32_t lo = 2 * i - (i & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const uint64_t a = buf[lo], b = buf[hi];
+        if ((a < b) == desc) { buf[lo] = b; buf[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int CAP>
+__device__ __forceinline__ void stage_flush_coh(Stage<CAP>& S, uint32_t* gcount, uint32_t gcap, uint32_t* gkey,
+                                                uint32_t* gidx, Ctl* ctl, bool force, uint32_t margin) {
+  __syncthreads();
+  const uint32_t n = S.n;
+  const bool doit = n != 0 && (force || n + margin > (uint32_t)CAP);
+  __syncthreads();
+  if (!doit) return;
+  if (threadIdx.x == 0) S.base = atomicAdd(gcount, n);
+  __syncthreads();
+  const uint32_t base = S.base;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (base + i < gcap) {
+      st_coh(&gkey[base + i], S.key[i]);
+      if (gidx) st_coh(&gidx[base + i], S.idx[i]);
+    } else {
+      ctl->err |= 16u;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.n = 0;
+  __syncthreads();
+}
+
+// Shared memory of the tail kernel, reused phase by phase.
+struct TailSmem {
+  union {
+    uint64_t sortbuf[kSmallCap];  // 64 KiB: the one-block LDS sorts
+    struct {
+      uint32_t hist[kBins];
+      Stage<1024> sq;
+      Stage<4096> sc;
+    } st;
+  } u;
+  uint32_t scan[kTailThreads];
+  uint32_t out[4];
+  uint32_t item;
+  int last;
+};
+
+// ---- phase protocol -------------------------------------------------------
+
+// Next chunk of phase `ph` for this block (block-uniform result); >= limit
+// when the phase has no chunk left.  A coherent read first keeps blocks that
+// arrive after the chunks are gone off the contended counter.
+__device__ __forceinline__ uint32_t claim(Phase* ph, uint32_t limit, TailSmem& sm) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t cur = ld_coh(&ph->claim);
+    sm.item = cur < limit ? atomicAdd(&ph->claim, 1u) : cur;
+  }
+  __syncthreads();
+  return sm.item;
+}
+
+// Reports the `mine` chunks this block completed; true in exactly one block,
+// the one whose report completes the phase.  All of this block's global
+// writes and atomics for those chunks have completed before the report.
+__device__ __forceinline__ bool report(Phase* ph, uint32_t mine, uint32_t nchunks, TailSmem& sm) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) sm.last = mine ? (atomicAdd(&ph->done, mine) + mine == nchunks) : 0;
+  __syncthreads();
+  return sm.last != 0;
+}
+
+__device__ __forceinline__ void raise_ready(Phase* ph) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) st_coh(&ph->ready, 1u);
+}
+
+// Completion time of phase i (device real-time clock, 100 MHz), for profiling.
+__device__ __forceinline__ void stamp(Ctl* ctl, int i) {
+  if (threadIdx.x == 0) ctl->tstamp[i] = __builtin_amdgcn_s_memrealtime();
+}
+
+__device__ __forceinline__ void wait_ready(Phase* ph, Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (ld_coh(&ph->ready) == 0u) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinLimit) {
+        atomicOr(&ctl->err, 64u);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void pub64(uint32_t* p, uint64_t v) {
+  st_coh(p, (uint32_t)v);
+  st_coh(p + 1, (uint32_t)(v >> 32));
+}
+__device__ __forceinline__ uint64_t get64(const uint32_t* p) {
+  return ((uint64_t)ld_coh(p + 1) << 32) | ld_coh(p);
+}
+
+// ---- multi-block radix select over a buffer written earlier in this kernel --
+// Phases ph[0..kPasses): one per digit.  Returns the rank-th largest composite
+// of (key[i], idx[i]), i < count, identically in every block.
+constexpr uint32_t kSelChunk = kTailThreads * 8;
+
+__device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t rank,
+                                       uint32_t (*hist)[kBins], Phase* ph, uint32_t* pubsel, Ctl* ctl,
+                                       TailSmem& sm) {
+  uint64_t prefix = 0, mask = 0;
+  uint32_t r = rank;
+  const uint32_t nchunks = (count + kSelChunk - 1) / kSelChunk;
+  if (nchunks == 0 || rank == 0 || rank > count) {  // inconsistent input: flag, never wait
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->err |= 1u;
+    return 0;
+  }
+  for (int p = 0; p < kPasses; ++p) {
+    for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
+    const int sh = pass_shift(p);
+    const uint32_t dm = (1u << pass_bits(p)) - 1;
+    const uint32_t kmask = (uint32_t)(mask >> 32), kpref = (uint32_t)(prefix >> 32);
+    const uint32_t imask = (uint32_t)mask, ipref = (uint32_t)prefix;
+    uint32_t mine = 0;
+    for (;;) {
+      const uint32_t c = claim(&ph[p], nchunks, sm);
+      if (c >= nchunks) break;
+      ++mine;
+#pragma unroll 2
+      for (uint32_t j = 0; j < kSelChunk; j += kTailThreads) {
+        const uint32_t i = c * kSelChunk + j + threadIdx.x;
+        if (i >= count) continue;
+        const uint32_t kk = ld_coh(&key[i]);
+        if ((kk & kmask) != kpref) continue;
+        uint64_t x = (uint64_t)kk << 32;
+        if (p >= 3) {
+          const uint32_t ip = ~ld_coh(&idx[i]);
+          if ((ip & imask) != ipref) continue;
+          x |= ip;
+        }
+        atomicAdd(&sm.u.st.hist[(uint32_t)(x >> sh) & dm], 1u);
+      }
+    }
+    __syncthreads();
+    if (mine)
+      for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
+        const uint32_t v = sm.u.st.hist[i];
+        if (v) atomicAdd(&hist[p][i], v);
+      }
+    if (report(&ph[p], mine, nchunks, sm)) {
+      tail_bucket(hist[p], r, sm.scan, sm.out);
+      if (threadIdx.x == 0) {
+        if (!sm.out[2]) ctl->err |= 1u;
+        pub64(pubsel, prefix | ((uint64_t)sm.out[0] << sh));
+        st_coh(pubsel + 2, sm.out[1]);
+      }
+      if (threadIdx.x == 0) ctl->tstamp[(ph - ctl->ph) + p] = __builtin_amdgcn_s_memrealtime();
+      raise_ready(&ph[p]);
+    }
+    wait_ready(&ph[p], ctl);
+    prefix = get64(pubsel);
+    mask |= (uint64_t)dm << sh;
+    r = ld_coh(pubsel + 2);
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// ---- block sort ----------------------------------------------------------------
+// Bitonic sort (descending) of P = E * kTailThreads composites held in
+// registers, element g = threadIdx.x * E + e.  Compare-exchange partners at
+// distance j < E are in the same thread (registers), E <= j < 64 E in another
+// lane of the same wave (lane shuffles), and only j >= 64 E go through LDS
+// with barriers.  Each element computes its own new value from its partner's.
+
+__device__ __forceinline__ uint64_t ce_pick(uint64_t mine, uint64_t other, bool lower, bool desc_block) {
+  // `lower`: this element has the lower index of the pair.  In a descending
+  // block the lower index keeps the larger value.
+  const bool keep_max = lower == desc_block;
+  const bool mine_gt = mine > other;
+  return keep_max ? (mine_gt ? mine : other) : (mine_gt ? other : mine);
+}
+
+// One compare-exchange stage of block size S and partner distance J, all
+// compile-time, so the element array stays in registers.
+template <int E, uint32_t S, uint32_t J>
+__device__ __forceinline__ void bs_stage(uint64_t (&v)[E], uint64_t* lds) {
+  if constexpr (J < (uint32_t)E) {
+    const uint32_t base = threadIdx.x * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & J) == 0) {
+        const bool desc_block = ((base + e) & S) == 0;  // (e, e|J) lie in one block of size S
+        const uint64_t a = v[e], b = v[e | J];
+        const bool a_gt = a > b;
+        const uint64_t hi = a_gt ? a : b, lo = a_gt ? b : a;
+        v[e] = desc_block ? hi : lo;
+        v[e | J] = desc_block ? lo : hi;
+      }
+    }
+  } else if constexpr (J < 64u * E) {
+    constexpr uint32_t m = J / E;  // lane distance
+    const bool lower = (lane_id() & m) == 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[e] = ce_pick(v[e], shfl_xor64(v[e], (int)m), lower, ((threadIdx.x * E + e) & S) == 0);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[threadIdx.x * E + e] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t g = threadIdx.x * E + e;
+      v[e] = ce_pick(v[e], lds[g ^ J], (g & J) == 0, (g & S) == 0);
+    }
+  }
+  if constexpr (J > 1) bs_stage<E, S, J / 2>(v, lds);
+}
+
+template <int E, uint32_t S>
+__device__ __forceinline__ void bs_size(uint64_t (&v)[E], uint64_t* lds) {
+  bs_stage<E, S, S / 2>(v, lds);
+  if constexpr (S < (uint32_t)E * kTailThreads) bs_size<E, S * 2>(v, lds);
+}
+
+template <int E>
+__device__ __forceinline__ void block_bitonic(uint64_t (&v)[E], uint64_t* lds) {
+  bs_size<E, 2>(v, lds);
+  __syncthreads();
+}
+
+// Sorts `count` (<= kSmallCap) composites read coherently from (key, idx) and
+// writes the first `limit` of them as outputs first_slot, first_slot+1, ...
+template <int DT, int E>
+__device__ __noinline__ void sort_and_write_e(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t first_slot,
+                                        uint32_t limit, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
+                                        uint32_t* out_kth, uint64_t* lds) {
+  uint64_t v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = threadIdx.x * E + e;
+    v[e] = g < count ? comp(ld_coh(&key[g]), ld_coh(&idx[g])) : 0ull;
+  }
+  block_bitonic<E>(v, lds);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = threadIdx.x * E + e;
+    if (g < limit) write_out<DT>(v[e], first_slot + g, k, out_vals, out_idx, out_kth);
+  }
+}
+
+template <int DT>
+__device__ inline void sort_and_write(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t first_slot,
+                                      uint32_t limit, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
+                                      uint32_t* out_kth, uint64_t* lds) {
+  if (count <= 1u * kTailThreads)
+    sort_and_write_e<DT, 1>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
+  else if (count <= 2u * kTailThreads)
+    sort_and_write_e<DT, 2>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
+  else if (count <= 4u * kTailThreads)
+    sort_and_write_e<DT, 4>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
+  else if (count <= 8u * kTailThreads)
+    sort_and_write_e<DT, 8>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
+  else
+    sort_and_write_e<DT, 16>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
+}
+
+// Per-block running max / min of survivor composites (LDS), merged into ctl
+// when the block leaves a phase; they size the output buckets.
+struct MinMax {
+  unsigned long long mx, nmn;
+};
+__device__ __forceinline__ void mm_init(MinMax& m) {
+  if (threadIdx.x == 0) { m.mx = 0ull; m.nmn = 0ull; }
+}
+__device__ __forceinline__ void mm_add(MinMax& m, bool pred, uint64_t c) {
+  if (pred) {
+    atomicMax(&m.mx, (unsigned long long)c);
+    atomicMax(&m.nmn, (unsigned long long)~c);
+  }
+}
+__device__ __forceinline__ void mm_flush(MinMax& m, Ctl* ctl) {
+  __syncthreads();
+  if (threadIdx.x == 0 && m.mx) {
+    atomicMax(reinterpret_cast<unsigned long long*>(&ctl->cmax), m.mx);
+    atomicMax(reinterpret_cast<unsigned long long*>(&ctl->ncmin), m.nmn);
+  }
+}
+
+// One block: sort survivors (<= kSmallCap) and write the first k.
+template <int DT>
+__device__ inline void small_output(const TailArgs& a, uint32_t nc, TailSmem& sm) {
+  sort_and_write<DT>(a.ckey, a.cidx, nc, 0, a.k, a.k, a.kth_only ? nullptr : a.out_vals,
+                     a.kth_only ? nullptr : a.out_idx, a.out_kth, sm.u.sortbuf);
+}
+
+enum { PH_H = 0, PH_Q = 1, PH_S = 2, PH_F1 = 3, PH_B1 = 4, PH_B2 = 5, PH_B3 = 6, PH_FSEL = 7, PH_FC = 13, PH_FS = 14,
+       PH_DSEL = 15 };
+constexpr uint32_t kWChunk = kTailThreads * 8;
+constexpr uint32_t kSChunk = kTailThreads * 4 * 8;
+constexpr uint32_t kGroup = 2048;  // output positions per sort group (a group holds < 2 kGroup)
+
+template <int DT, int BETA, bool VEC>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
+  __shared__ TailSmem sm;
+  __shared__ MinMax mm;
+  Ctl* ctl = a.ctl;
+  Phase* ph = ctl->ph;
+  if (blockIdx.x == 0) stamp(ctl, kPhases + 1);
+
+  // ---- threshold ---------------------------------------------------------------
+  // Rule 2 needs only a lower bound of the kD-th delegate t.  The delegate pass
+  // left the bin holding it, under the better of two monotone maps; its lowest
+  // key t' works (as composite T = t' << 32, below every element with that
+  // key), or, when the bin is crowded, the lowest key of the finer sub-bin
+  // holding t.  m = the delegates ranked >= T bounds the survivors by
+  // floor(m/beta)*2^alpha + m, so T is kept only while m <= kD + slack (the
+  // buffers are sized for that); otherwise -- massive ties -- the exact t is
+  // found by a radix select over the delegates.
+  uint64_t T = 0;
+  if (!a.all) {
+    const uint32_t lo = ctl->cut_lo, hi = ctl->cut_hi;
+    const uint32_t crowd = (1u << 22) >> (a.alpha < 22 ? a.alpha : 22);
+    const uint64_t limit = (uint64_t)a.kD + a.slack;
+    uint64_t m = (uint64_t)a.kD - ctl->cut_rank + ctl->cut_count;
+    const bool refine = hi > lo && (m > limit || ctl->cut_count > (crowd > 256u ? crowd : 256u));
+    uint32_t tkey = lo;
+    if (refine) {
+      const uint32_t fsh = bitlen32(hi - lo) > 11u ? bitlen32(hi - lo) - 11u : 0u;
+      for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
+      const uint32_t nchunks = (uint32_t)((a.nd + kWChunk - 1) / kWChunk);
+      uint32_t mine = 0;
+      for (;;) {
+        const uint32_t c = claim(&ph[PH_H], nchunks, sm);
+        if (c >= nchunks) break;
+        ++mine;
+        for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
+          const uint64_t i = (uint64_t)c * kWChunk + j + threadIdx.x;
+          if (i < a.nd) {
+            const uint32_t kk = a.dkey[i];
+            if (kk >= lo && kk <= hi && a.didx[i] != kInvalid) atomicAdd(&sm.u.st.hist[(kk - lo) >> fsh], 1u);
+          }
+        }
+      }
+      __syncthreads();
+      if (mine)
+        for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
+          const uint32_t v = sm.u.st.hist[i];
+          if (v) atomicAdd(&ctl->histH[i], v);
+        }
+      if (report(&ph[PH_H], mine, nchunks, sm)) {
+        tail_bucket(ctl->histH, ctl->cut_rank, sm.scan, sm.out);
+        if (threadIdx.x == 0) {
+          // padding entries (key 0) were left out of the sub-bins; if that leaves
+          // the rank unreached, keep the whole bin
+          const bool ok = sm.out[2] != 0;
+          st_coh(&ctl->tpub[0], ok ? lo + (sm.out[0] << fsh) : lo);
+          st_coh(&ctl->tpub[1], ok ? a.kD - sm.out[1] + sm.out[3] : (uint32_t)(m < 0xFFFFFFFFull ? m : 0xFFFFFFFFull));
+        }
+        stamp(ctl, PH_H);
+        raise_ready(&ph[PH_H]);
+      }
+      wait_ready(&ph[PH_H], ctl);
+      tkey = ld_coh(&ctl->tpub[0]);
+      m = ld_coh(&ctl->tpub[1]);
+    }
+    if (m <= limit) {
+      T = (uint64_t)tkey << 32;
+    } else {
+      T = tail_select(a.dkey, a.didx, (uint32_t)a.nd, a.kD, ctl->histW, &ph[PH_DSEL], ctl->selpub, ctl, sm);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->selD.prefix = T;  // host statistics
+
+  // ---- Q: Rule 3 against T -----------------------------------------------------
+  // Subrange s is re-read iff its beta-th delegate ranks above T; otherwise its
+  // delegates ranked >= T are survivors.  (T = 0 when there are fewer real
+  // delegates than k: every subrange with beta real delegates is re-read.)
+  if (threadIdx.x == 0) { sm.u.st.sq.n = 0; sm.u.st.sc.n = 0; }
+  mm_init(mm);
+  {
+    constexpr uint32_t kQChunk = kTailThreads * 8;
+    const uint32_t nchunks = (uint32_t)((a.S + kQChunk - 1) / kQChunk);
+    uint32_t mine = 0;
+    uint32_t c = 0, sub = 8;
+    for (;;) {
+      if (sub == 8) {
+        c = claim(&ph[PH_Q], nchunks, sm);
+        if (c >= nchunks) break;
+        ++mine;
+        sub = 0;
+      }
+      const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)(sub++) * kTailThreads + threadIdx.x;
+      const bool ok = s < a.S;
+      bool scan = false;
+      if (ok) {
+        const uint64_t ds = s * BETA + BETA - 1;
+        scan = comp(a.dkey[ds], a.didx[ds]) > T && a.didx[ds] != kInvalid;
+      }
+      stage_push(sm.u.st.sq, scan, (uint32_t)s, 0u);
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+        bool take = false;
+        uint32_t kk = 0, ii = 0;
+        if (ok && !scan) {
+          kk = a.dkey[s * BETA + j];
+          ii = a.didx[s * BETA + j];
+          take = ii != kInvalid && comp(kk, ii) >= T;
+        }
+        mm_add(mm, take, comp(kk, ii));
+        stage_push(sm.u.st.sc, take, kk, ii);
+      }
+      stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
+      stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * BETA);
+    }
+    stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, true, 0);
+    stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, true, 0);
+    mm_flush(mm, ctl);
+    if (report(&ph[PH_Q], mine, nchunks, sm)) {
+      stamp(ctl, PH_Q);
+      raise_ready(&ph[PH_Q]);
+    }
+    wait_ready(&ph[PH_Q], ctl);
+  }
+
+  // ---- S: the virtual concatenated vector of the queued subranges -----------
+  bool s_final = false;
+  {
+    const uint32_t nq = ld_coh(&ctl->nq) < ctl->cap_q ? ld_coh(&ctl->nq) : ctl->cap_q;
+    const uint64_t total = (uint64_t)nq << a.alpha;
+    const uint32_t nchunks = (uint32_t)((total + kSChunk - 1) / kSChunk);
+    const uint64_t lmask = (1ull << a.alpha) - 1;
+    if (threadIdx.x == 0) sm.u.st.sc.n = 0;
+    mm_init(mm);
+    uint32_t mine = 0;
+    for (;;) {
+      const uint32_t ch = claim(&ph[PH_S], nchunks, sm);
+      if (ch >= nchunks) break;
+      ++mine;
+      for (uint32_t j = 0; j < kSChunk; j += kTailThreads * 4) {
+        const uint64_t e = (uint64_t)ch * kSChunk + j + threadIdx.x * 4;
+        uint32_t v[4];
+        uint64_t pos[4];
+        bool in[4];
+        if (VEC && a.alpha >= 2) {
+          const uint64_t p = e < total ? ((uint64_t)ld_coh(&a.Q[e >> a.alpha]) << a.alpha) + (e & lmask) : a.n;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) { pos[c] = p + c; in[c] = p + c < a.n; }
+          if (p + 4 <= a.n) {
+            load4<DT, true>(a.keys, p, v);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = in[c] ? a.keys[p + c] : 0u;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint64_t ec = e + c;
+            pos[c] = ec < total ? ((uint64_t)ld_coh(&a.Q[ec >> a.alpha]) << a.alpha) + (ec & lmask) : a.n;
+            in[c] = pos[c] < a.n;
+            v[c] = in[c] ? a.keys[pos[c]] : 0u;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t kk = enc<DT>(v[c]);
+          const uint64_t cc = comp(kk, (uint32_t)pos[c]);
+          const bool take = in[c] && cc >= T;
+          mm_add(mm, take, cc);
+          stage_push(sm.u.st.sc, take, kk, (uint32_t)pos[c]);
+        }
+        stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
+      }
+    }
+    stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, true, 0);
+    mm_flush(mm, ctl);
+    if (report(&ph[PH_S], mine, nchunks, sm)) {
+      stamp(ctl, PH_S);
+      raise_ready(&ph[PH_S]);
+      s_final = true;
+    }
+    if (nchunks) wait_ready(&ph[PH_S], ctl);
+  }
+  if (a.stop_after_scan) return;
+
+  // ---- F: the output ---------------------------------------------------------
+  const uint32_t nc = ld_coh(&ctl->nc) < ctl->cap_c ? ld_coh(&ctl->nc) : ctl->cap_c;
+  if (nc < a.k) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->err |= 2u;
+    return;
+  }
+  if (nc <= (uint32_t)kSmallCap) {
+    // the block that completed the re-read sorts (or any one block if nothing was re-read)
+    const bool had_scan = ld_coh(&ctl->nq) != 0u;
+    if (had_scan ? !s_final : claim(&ph[PH_F1], 1, sm) != 0) return;
+    small_output<DT>(a, nc, sm);
+    stamp(ctl, PH_F1);
+    return;
+  }
+
+  // Many survivors: bucket them by the top 11 significant bits of
+  // (composite - smallest), highest bucket first, scatter, and sort groups of
+  // buckets (about kGroup output slots each) in LDS.
+  const uint64_t cmax = ld_coh64(&ctl->cmax), cmin = ~ld_coh64(&ctl->ncmin);
+  const uint32_t bsh = bitlen64(cmax - cmin) > 11u ? bitlen64(cmax - cmin) - 11u : 0u;
+  {
+    for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
+    const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
+    uint32_t mine = 0;
+    for (;;) {
+      const uint32_t c = claim(&ph[PH_B1], nchunks, sm);
+      if (c >= nchunks) break;
+      ++mine;
+      for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
+        const uint32_t i = c * kWChunk + j + threadIdx.x;
+        if (i < nc) {
+          const uint64_t x = comp(ld_coh(&a.ckey[i]), ld_coh(&a.cidx[i]));
+          atomicAdd(&sm.u.st.hist[2047u - (uint32_t)((x - cmin) >> bsh)], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    if (mine)
+      for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
+        const uint32_t v = sm.u.st.hist[i];
+        if (v) atomicAdd(&ctl->bcount[i], v);
+      }
+    if (report(&ph[PH_B1], mine, nchunks, sm)) {
+      // Bucket offsets (exclusive scan, bucket 0 = highest composites) and the
+      // sort groups: group w holds the buckets whose first slot lies in
+      // [w*kGroup, (w+1)*kGroup); gfirst[w] is its first bucket and
+      // gfirst[nwin] marks the end.  Bucket b opens every window after the
+      // previous bucket's start window up to its own.
+      constexpr int PER = kBins / kTailThreads;
+      uint32_t* lb = sm.u.st.hist;  // the local histogram is flushed: reuse for offsets
+      const int t0 = threadIdx.x * PER;
+      uint32_t cnt[PER], sum = 0, big = 0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        cnt[j] = ld_coh(&ctl->bcount[t0 + j]);
+        sum += cnt[j];
+        big = cnt[j] > big ? cnt[j] : big;
+      }
+      sm.scan[threadIdx.x] = sum;
+      __syncthreads();
+      for (int o = 1; o < kTailThreads; o <<= 1) {
+        const uint32_t x = threadIdx.x >= (unsigned)o ? sm.scan[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sm.scan[threadIdx.x] += x;
+        __syncthreads();
+      }
+      uint32_t off = sm.scan[threadIdx.x] - sum;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        lb[t0 + j] = off;
+        st_coh(&ctl->boff[t0 + j], off);
+        off += cnt[j];
+      }
+      if (threadIdx.x == kTailThreads - 1) st_coh(&ctl->boff[kBins], off);
+      __syncthreads();
+      const uint32_t nwin = (nc + kGroup - 1) / kGroup;
+      if (big > kGroup || nwin > (uint32_t)kBins) atomicOr(&ctl->bigbucket, 1u);
+      if (nwin <= (uint32_t)kBins) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const uint32_t b = t0 + j;
+          const int64_t wb = lb[b] / kGroup;
+          const int64_t wp = b == 0 ? -1 : (int64_t)(lb[b - 1] / kGroup);
+          for (int64_t w = wp + 1; w <= wb && w <= (int64_t)nwin; ++w) st_coh(&ctl->gfirst[w], b);
+        }
+        if (threadIdx.x == kTailThreads - 1)
+          for (uint32_t w = lb[kBins - 1] / kGroup + 1; w <= nwin; ++w) st_coh(&ctl->gfirst[w], (uint32_t)kBins);
+        if (threadIdx.x == 0) st_coh(&ctl->ngroups, nwin);
+      }
+      stamp(ctl, PH_B1);
+      raise_ready(&ph[PH_B1]);
+    }
+    wait_ready(&ph[PH_B1], ctl);
+  }
+  if (ld_coh(&ctl->bigbucket) == 0u) {
+    // B2: scatter into bucket order
+    {
+      const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
+      uint32_t mine = 0;
+      for (;;) {
+        const uint32_t c = claim(&ph[PH_B2], nchunks, sm);
+        if (c >= nchunks) break;
+        ++mine;
+        for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
+          const uint32_t i = c * kWChunk + j + threadIdx.x;
+          if (i < nc) {
+            const uint32_t kk = ld_coh(&a.ckey[i]), ii = ld_coh(&a.cidx[i]);
+            const uint32_t b = 2047u - (uint32_t)((comp(kk, ii) - cmin) >> bsh);
+            const uint32_t slot = ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], 1u);
+            if (slot < a.cap_s) {
+              st_coh(&a.skey[slot], kk);
+              st_coh(&a.sidx[slot], ii);
+            } else {
+              ctl->err |= 16u;
+            }
+          }
+        }
+      }
+      if (report(&ph[PH_B2], mine, nchunks, sm)) {
+        stamp(ctl, PH_B2);
+        raise_ready(&ph[PH_B2]);
+      }
+      wait_ready(&ph[PH_B2], ctl);
+    }
+    // B3: sort each group in LDS, write the slots below k
+    {
+      const uint32_t ng = ld_coh(&ctl->ngroups);
+      uint32_t mine = 0;
+      for (;;) {
+        const uint32_t gi = claim(&ph[PH_B3], ng, sm);
+        if (gi >= ng) break;
+        ++mine;
+        const uint32_t lo = ld_coh(&ctl->boff[ld_coh(&ctl->gfirst[gi])]);
+        const uint32_t hi = ld_coh(&ctl->boff[ld_coh(&ctl->gfirst[gi + 1])]);
+        if (lo >= a.k || hi <= lo) continue;
+        const uint32_t cnt = hi - lo;
+        if (cnt > (uint32_t)kSmallCap) {
+          if (threadIdx.x == 0) ctl->err |= 128u;
+          continue;
+        }
+        sort_and_write<DT>(a.skey + lo, a.sidx + lo, cnt, lo, a.k - lo < cnt ? a.k - lo : cnt, a.k,
+                           a.kth_only ? nullptr : a.out_vals, a.kth_only ? nullptr : a.out_idx, a.out_kth,
+                           sm.u.sortbuf);
+      }
+      if (report(&ph[PH_B3], mine, ng, sm)) stamp(ctl, PH_B3);
+    }
+    return;
+  }
+
+  // Fallback for an overfull bucket (massive ties): exact radix select of the
+  // k-th survivor, exact compaction, then an LDS sort (k <= kSmallCap) or the
+  // separate merge-sort kernels.
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->need_merge = a.big_sort ? 1u : 0u;
+  const uint64_t Tk = tail_select(a.ckey, a.cidx, nc, a.k, ctl->histC, &ph[PH_FSEL], ctl->selpub + 4, ctl, sm);
+  if (a.kth_only) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.out_kth) *a.out_kth = dec<DT>(comp_key(Tk));
+    return;
+  }
+  {
+    if (threadIdx.x == 0) sm.u.st.sc.n = 0;
+    const uint32_t nch = (nc + kWChunk - 1) / kWChunk;
+    uint32_t mine = 0;
+    for (;;) {
+      const uint32_t c = claim(&ph[PH_FC], nch, sm);
+      if (c >= nch) break;
+      ++mine;
+      for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
+        const uint32_t i = c * kWChunk + j + threadIdx.x;
+        uint64_t x = 0;
+        if (i < nc) x = comp(ld_coh(&a.ckey[i]), ld_coh(&a.cidx[i]));
+        stage_push(sm.u.st.sc, i < nc && x >= Tk, comp_key(x), comp_pos(x));
+      }
+      stage_flush_coh(sm.u.st.sc, &ctl->nout, a.k, a.okey, a.oidx, ctl, false, kWChunk);
+    }
+    stage_flush_coh(sm.u.st.sc, &ctl->nout, a.k, a.okey, a.oidx, ctl, true, 0);
+    if (report(&ph[PH_FC], mine, nch, sm)) {
+      stamp(ctl, PH_FC);
+      raise_ready(&ph[PH_FC]);
+    }
+    if (a.big_sort) return;  // k > kSmallCap: the merge-sort kernels follow
+    wait_ready(&ph[PH_FC], ctl);
+  }
+  if (claim(&ph[PH_FS], 1, sm) != 0) return;
+  sort_and_write<DT>(a.okey, a.oidx, a.k, 0, a.k, a.k, a.out_vals, a.out_idx, a.out_kth, sm.u.sortbuf);
+  stamp(ctl, PH_FS);
+}
+
+}  // namespace drtopk

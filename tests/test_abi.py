@@ -34,7 +34,7 @@ def test_planner():
     assert drt.plan(2 ** 30, 1024) == drt.Plan(1, 11, 1)
     assert drt.plan(2 ** 20, 1024) == drt.Plan(1, 6, 1)
     p = drt.plan(2 ** 30, 131072)
-    assert p.mode == 1 and p.alpha == 8
+    assert p.mode == 1 and p.beta == 2 and p.alpha == 10  # beta = 2 shifts Rule 4's alpha by 2
     # small inputs and large k/n fall back to a plain radix select
     assert drt.plan(4096, 7).mode == 2
     assert drt.plan(10 ** 6, 10 ** 5).mode == 2

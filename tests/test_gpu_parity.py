@@ -31,7 +31,8 @@ def dev(x: np.ndarray):
 
 
 def run_topk(x, k, **kw):
-    vals, idx = drt.topk_select(dev(x), k, **kw)[:2]
+    # stats=True synchronises and raises if a kernel flagged an internal inconsistency
+    vals, idx = drt.topk_select(dev(x), k, stats=True, **kw)[:2]
     torch.cuda.synchronize()
     return to_np(vals), to_np(idx)
 
@@ -96,13 +97,44 @@ def test_delegate_vector_stage(kind):
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_candidate_stage(kind):
+    """Survivors of the filter.  The one-kernel-per-step tail uses the exact
+    k-th delegate t and must keep exactly the oracle's candidate set; the
+    default tail uses a key t' <= t and must keep exactly {i : key[i] >= t'},
+    a superset of the oracle's set."""
     n = (1 << 17) + 3
     x, dt = synth.keys(kind, n, 12)
+    rk = oracle.rank_key(x, dt)
     for alpha, beta, k in [(4, 1, 50), (6, 2, 500), (8, 1, 3000), (9, 4, 3000), (5, 8, 64), (2, 1, 7)]:
-        say("candidates", kind, alpha, beta, k)
-        got = np.sort(to_np(drt.candidates(dev(x), k, alpha, beta)).view(np.uint32).astype(np.int64))
         _, _, info = stages.method_topk(x, k, dt, alpha, beta)
+        say("candidates", kind, alpha, beta, k, "variant 1")
+        got, _ = drt.candidates(dev(x), k, alpha, beta, variant=1)
+        got = np.sort(to_np(got).view(np.uint32).astype(np.int64))
         assert (got == info["candidates"]).all(), (kind, alpha, beta, k, got.size, info["candidates"].size)
+        say("candidates", kind, alpha, beta, k, "variant 0")
+        got, (tbits, tpos) = drt.candidates(dev(x), k, alpha, beta, variant=0)
+        got = np.sort(to_np(got).view(np.uint32).astype(np.int64))
+        tv = oracle.rank_key(np.array([tbits], dtype=np.uint32).view(x.dtype), dt)[0]
+        pos = np.arange(n)
+        want = np.flatnonzero((rk > tv) | ((rk == tv) & (pos <= tpos)))
+        assert (got == want).all(), (kind, alpha, beta, k, got.size, want.size)
+        assert np.isin(info["candidates"], got).all()
+        if info["t"] is not None:  # Rule 2: the threshold ranks no higher than the k-th delegate
+            assert tv < info["t"][0] or (tv == info["t"][0] and tpos >= info["t"][1])
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_tail_variants_agree(kind):
+    """The cooperative tail kernel and the one-kernel-per-step tail give identical output."""
+    for n, k, alpha, beta in [((1 << 20) + 9, 1, None, None), ((1 << 20) + 9, 1024, None, None),
+                              ((1 << 21) + 1, 20000, None, None), ((1 << 20) + 9, 3000, 8, 1),
+                              ((1 << 20) + 9, 3000, 6, 4), (300000, 150, 2, 8)]:
+        x, dt = synth.keys(kind, n, 77)
+        want = oracle.topk_reference(x, k, dt)
+        for variant in (0, 1):
+            say(kind, n, k, alpha, beta, "variant", variant)
+            vals, idx = run_topk(x, k, alpha=alpha, beta=beta, mode=1, variant=variant)
+            assert (idx.view(np.uint32) == want[1]).all(), (kind, n, k, alpha, beta, variant)
+            assert (vals.view(np.uint32) == want[0].view(np.uint32)).all()
 
 
 def test_plain_radix_mode():
