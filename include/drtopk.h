@@ -78,9 +78,48 @@ typedef struct {
 } drtopk_problem_t;
 
 /* Many independent top-k problems (the paper's Section 1 problem, applied to
- * each).  `problems` is a HOST array of `count` descriptors, copied during the
- * call.  Results equal topk_select on each problem alone, bit for bit. */
+ * each).  `problems` is a HOST array of `count` descriptors, read during the
+ * call (the caller may reuse it on return).  Each problem obeys topk_select's
+ * rules, except that out_vals may be NULL when out_kth is not (k-selection
+ * only).  Results equal topk_select / kth_select on each problem alone, bit
+ * for bit.  Problems with n <= 2^22 and k <= 2048 run in one persistent
+ * launch, one workgroup per problem at a time, largest first (the delegate
+ * method of Sections 4-5 inside the workgroup's LDS); larger ones run one
+ * after another through the single-problem path, on the same stream.  Any
+ * invalid descriptor fails the whole call with DRTOPK_EINVAL before any work
+ * is enqueued.  Output buffers of different problems must not overlap. */
 int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream);
+
+/* Autotuner table (Rule 4's subrange size and Rule 3's beta, measured rather
+ * than modelled).  An entry applies to problems of one form whose
+ * floor(log2 n) and floor(log2 k) equal lg_n and lg_k:
+ *   form 0 (DRTOPK_FORM_SINGLE): topk_select / kth_select planning, alpha and
+ *          beta as in drtopk_options_t (explicit options still win);
+ *   form 1 (DRTOPK_FORM_BATCHED): the subrange exponent of a batched problem
+ *          owned by one workgroup (beta is 1 there; the kernel raises alpha
+ *          until the delegate vector fits its LDS).
+ * Problems with no entry use Rule 4 (const 3).  drtopk_tune_set replaces the
+ * whole table (count 0 clears it); entries are validated (alpha 0..24, beta
+ * 1/2/4/8) and copied.  The table is process-wide. */
+enum { DRTOPK_FORM_SINGLE = 0, DRTOPK_FORM_BATCHED = 1 };
+typedef struct {
+  int32_t form;
+  int32_t lg_n;
+  int32_t lg_k;
+  int32_t alpha;
+  int32_t beta;
+} drtopk_tune_t;
+int drtopk_tune_set(const drtopk_tune_t* entries, uint32_t count);
+/* Copies up to `cap` entries to `out` (host) and the table size to *count. */
+int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count);
+
+/* How a batched problem of this shape is run (no device work):
+ *   *route 0 = single-problem path, 1 = sorted outright in the workgroup,
+ *          2 = delegate method in the workgroup with subrange exponent
+ *          *alpha, 3 = workgroup radix select without delegates.
+ * Route 2 falls back to route 3 on the device when the survivors of an
+ * input exceed the workgroup's capacity (8192). */
+int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha);
 
 /* Explicit method parameters (for tests, tuning and ablations).
  *   alpha  subrange = 2^alpha elements (Section 5.1); -1 = planner's choice

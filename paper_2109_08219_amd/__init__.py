@@ -18,6 +18,7 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdrtopk.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "drtopk.h")
+TUNING_PATH = os.path.join(HERE, "tuning.json")  # written by paper_2109_08219_amd.tune
 
 U32, F32 = 0, 1
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported"}
@@ -40,6 +41,11 @@ class Stats(ctypes.Structure):
                 ("scanned", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
                 ("t_key_bits", ctypes.c_uint32), ("t_idx", ctypes.c_uint32),
                 ("step_ns", ctypes.c_uint32 * 20), ("err_flags", ctypes.c_uint32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("lg_n", ctypes.c_int32), ("lg_k", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -73,6 +79,9 @@ def lib() -> ctypes.CDLL:
             "drtopk_timing_enable": [i32],
             "drtopk_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)],
+            "drtopk_tune_set": [ctypes.POINTER(Tune), u32],
+            "drtopk_tune_get": [ctypes.POINTER(Tune), u32, ctypes.POINTER(u32)],
+            "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -83,6 +92,8 @@ def lib() -> ctypes.CDLL:
         L.drtopk_version.argtypes = []
         L.drtopk_version.restype = ctypes.c_char_p
         _lib = L
+        if os.path.exists(TUNING_PATH):
+            load_tuning(TUNING_PATH)
     return _lib
 
 
@@ -172,22 +183,75 @@ def kth_select(keys, k: int, out=None, *, dtype=None, stream=None):
     return out
 
 
+class Batch:
+    """A fixed set of top-k problems with packed device outputs, reusable across calls.
+
+    problems: list of (keys, k) or (keys, k, dtype).  All outputs of problem i live in
+    three packed int32 buffers: vals[off[i] : off[i] + k_i] (bit patterns of the keys'
+    dtype), idx[same range] (uint32 positions) and kth[i].  kth_only=True asks for the
+    k-th values alone (no vals / idx buffers).  The descriptors are built once; run()
+    enqueues one topk_select_batched call on `stream`.
+    """
+
+    def __init__(self, problems, *, kth_only: bool = False):
+        torch = _torch()
+        self.count = len(problems)
+        self.keys = [pr[0] for pr in problems]
+        self.ks = [int(pr[1]) for pr in problems]
+        self.codes = [_prep(pr[0], pr[2] if len(pr) > 2 else None) for pr in problems]
+        self.kth_only = kth_only
+        dev = self.keys[0].device if self.keys else torch.device("cuda")
+        self.off = [0] * self.count
+        total = 0
+        for i, k in enumerate(self.ks):
+            self.off[i] = total
+            total += k
+        self.total_k = total
+        self.kth = torch.empty(max(1, self.count), dtype=torch.int32, device=dev)
+        if kth_only:
+            self.vals = self.idx = None
+        else:
+            self.vals = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+            self.idx = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        self._descs = (Problem * max(1, self.count))()
+        vb = self.vals.data_ptr() if self.vals is not None else 0
+        ib = self.idx.data_ptr() if self.idx is not None else 0
+        kb = self.kth.data_ptr()
+        for i in range(self.count):
+            kt = self.keys[i]
+            self._descs[i] = Problem(kt.data_ptr(), kt.numel(), self.ks[i], self.codes[i],
+                                     vb + 4 * self.off[i] if vb else None,
+                                     ib + 4 * self.off[i] if ib else None, kb + 4 * i)
+
+    def run(self, stream=None) -> None:
+        rc = lib().topk_select_batched(self._descs, self.count, _stream(stream))
+        _check(rc, "topk_select_batched")
+
+    def _as_keys(self, t, i):
+        return t.view(self.keys[i].dtype)
+
+    def values(self, i: int):
+        return self._as_keys(self.vals[self.off[i]:self.off[i] + self.ks[i]], i)
+
+    def indices(self, i: int):
+        return self.idx[self.off[i]:self.off[i] + self.ks[i]]
+
+    def kth_value(self, i: int):
+        return self._as_keys(self.kth[i:i + 1], i)
+
+
 def topk_select_batched(problems, *, stream=None):
     """problems: list of (keys, k) or (keys, k, dtype).  Returns a list of (values, indices, kth)."""
-    torch = _torch()
-    descs = (Problem * max(1, len(problems)))()
-    outs = []
-    for i, pr in enumerate(problems):
-        keys, k = pr[0], pr[1]
-        code = _prep(keys, pr[2] if len(pr) > 2 else None)
-        v = torch.empty(k, dtype=keys.dtype, device=keys.device)
-        ix = torch.empty(k, dtype=torch.int32, device=keys.device)
-        kth = torch.empty(1, dtype=keys.dtype, device=keys.device)
-        descs[i] = Problem(keys.data_ptr(), keys.numel(), k, code, v.data_ptr(), ix.data_ptr(), kth.data_ptr())
-        outs.append((v, ix, kth))
-    rc = lib().topk_select_batched(descs, len(problems), _stream(stream))
-    _check(rc, "topk_select_batched")
-    return outs
+    b = Batch(problems)
+    b.run(stream)
+    return [(b.values(i), b.indices(i), b.kth_value(i)) for i in range(b.count)]
+
+
+def kth_select_batched(problems, *, stream=None):
+    """problems as for topk_select_batched.  Returns a list of 1-element k-th value tensors."""
+    b = Batch(problems, kth_only=True)
+    b.run(stream)
+    return [b.kth_value(i) for i in range(b.count)]
 
 
 def delegates(keys, alpha: int, beta: int, *, dtype=None, stream=None):
@@ -232,6 +296,42 @@ def plan(n: int, k: int, dtype: str = "u32") -> Plan:
     o = Options()
     _check(lib().drtopk_plan(n, k, {"u32": U32, "f32": F32}[dtype], ctypes.byref(o)), "drtopk_plan")
     return Plan(o.mode, o.alpha, o.beta)
+
+
+FORM_SINGLE, FORM_BATCHED = 0, 1
+
+
+def tune_set(entries) -> None:
+    """Replaces the autotuner table: entries of (form, lg_n, lg_k, alpha, beta)."""
+    entries = list(entries)
+    arr = (Tune * max(1, len(entries)))(*[Tune(*map(int, e)) for e in entries])
+    _check(lib().drtopk_tune_set(arr, len(entries)), "drtopk_tune_set")
+
+
+def tune_get() -> list[tuple[int, int, int, int, int]]:
+    n = ctypes.c_uint32()
+    _check(lib().drtopk_tune_get(None, 0, ctypes.byref(n)), "drtopk_tune_get")
+    arr = (Tune * max(1, n.value))()
+    _check(lib().drtopk_tune_get(arr, n.value, ctypes.byref(n)), "drtopk_tune_get")
+    return [(e.form, e.lg_n, e.lg_k, e.alpha, e.beta) for e in arr[:n.value]]
+
+
+def load_tuning(path: str = TUNING_PATH) -> int:
+    """Loads a tuning table written by paper_2109_08219_amd.tune; returns its entry count."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    entries = [(e["form"], e["lg_n"], e["lg_k"], e["alpha"], e["beta"]) for e in doc["entries"]]
+    tune_set(entries)
+    return len(entries)
+
+
+def batched_route(n: int, k: int) -> tuple[int, int]:
+    """(route, alpha) of a batched problem: route 0 single-problem path, 1 sorted in the
+    workgroup, 2 delegate method in the workgroup (alpha), 3 workgroup radix select."""
+    r, a = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().drtopk_batched_alpha(n, k, ctypes.byref(r), ctypes.byref(a)), "drtopk_batched_alpha")
+    return r.value, a.value
 
 
 def release_workspace() -> None:

@@ -8,12 +8,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdrtopk.so")
 SOURCES = [os.path.join(HERE, "csrc", "drtopk.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "internal.h"), os.path.join(HERE, "csrc", "kernels.h"),
-           os.path.join(ROOT, "include", "drtopk.h")]
+HEADERS = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc")) if f.endswith(".h"))
+HEADERS.append(os.path.join(ROOT, "include", "drtopk.h"))
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed fp32 ops stay off on this target (see the design notes)
+    # no packed fp32 instructions in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

@@ -10,6 +10,7 @@
 // kernel checks a device-side gate and returns at once when not needed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +24,7 @@
 #include "drtopk.h"
 #include "kernels.h"
 #include "tail.h"
+#include "batched.h"
 
 namespace drtopk {
 namespace {
@@ -64,6 +66,24 @@ int default_beta(uint64_t n, uint32_t k) {
 
 bool valid_beta(int b) { return b == 1 || b == 2 || b == 4 || b == 8; }
 
+int floor_log2(uint64_t x) { return 63 - __builtin_clzll(x); }
+
+// Autotuner table: measured (alpha, beta) per (form, floor log2 n, floor log2 k).
+std::mutex g_tune_mu;
+std::vector<drtopk_tune_t> g_tune;
+
+bool tune_lookup(int form, uint64_t n, uint32_t k, int* alpha, int* beta) {
+  const int ln = floor_log2(n), lk = floor_log2(k);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (e.form == form && e.lg_n == ln && e.lg_k == lk) {
+      *alpha = e.alpha;
+      *beta = e.beta;
+      return true;
+    }
+  return false;
+}
+
 int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P) {
   Plan p;
   p.n = n;
@@ -77,9 +97,13 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
   p.variant = opt ? opt->variant : 0;
   if (p.variant < 0 || p.variant > 1) return DRTOPK_EINVAL;
   if (mode == 1) {
-    p.beta = (opt && opt->beta > 0) ? opt->beta : default_beta(n, k);
+    int ta = -1, tb = 0;
+    if (!tune_lookup(DRTOPK_FORM_SINGLE, n, k, &ta, &tb)) ta = -1, tb = 0;
+    p.beta = (opt && opt->beta > 0) ? opt->beta : tb > 0 ? tb : default_beta(n, k);
     if (!valid_beta(p.beta)) return DRTOPK_EINVAL;
-    p.alpha = (opt && opt->alpha >= 0) ? opt->alpha : rule_alpha(n, k) + (p.beta >= 2 ? 2 : 0);
+    p.alpha = (opt && opt->alpha >= 0) ? opt->alpha
+              : ta >= 0                ? ta
+                                       : rule_alpha(n, k) + (p.beta >= 2 ? 2 : 0);
     if (p.alpha > 24) p.alpha = 24;
     if (p.alpha > 24) return DRTOPK_EINVAL;
     const uint64_t L = 1ull << p.alpha;
@@ -144,6 +168,14 @@ struct Workspace {
   std::mutex mu;
   void* ptr = nullptr;
   size_t bytes = 0;
+  // batched launches: claim counter + descriptors on the device, staged
+  // through a pinned host buffer whose last copy `bev` marks
+  void* bdev = nullptr;
+  size_t bdev_bytes = 0;
+  void* bhost = nullptr;
+  size_t bhost_bytes = 0;
+  hipEvent_t bev = nullptr;
+  bool bev_pending = false;
 };
 
 std::mutex g_mu;
@@ -176,6 +208,46 @@ int ensure_bytes(Workspace* ws, size_t need) {
   }
   ws->ptr = p;
   ws->bytes = want;
+  return DRTOPK_OK;
+}
+
+// Called with ws->mu held: room for `need` bytes of batch descriptors on both
+// sides; the pinned buffer is free to overwrite on return.
+int ensure_batch_bytes(Workspace* ws, size_t need) {
+  if (ws->bev_pending) {
+    if (hipEventSynchronize(ws->bev) != hipSuccess) return DRTOPK_EDEVICE;
+    ws->bev_pending = false;
+  }
+  if (!ws->bev && hipEventCreateWithFlags(&ws->bev, hipEventDisableTiming) != hipSuccess) {
+    ws->bev = nullptr;
+    return DRTOPK_EDEVICE;
+  }
+  if (ws->bdev_bytes < need) {
+    if (ws->bdev) {
+      if (hipFree(ws->bdev) != hipSuccess) return DRTOPK_EDEVICE;
+      ws->bdev = nullptr;
+      ws->bdev_bytes = 0;
+    }
+    if (hipMalloc(&ws->bdev, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ws->bdev = nullptr;
+      return DRTOPK_ENOMEM;
+    }
+    ws->bdev_bytes = need;
+  }
+  if (ws->bhost_bytes < need) {
+    if (ws->bhost) {
+      if (hipHostFree(ws->bhost) != hipSuccess) return DRTOPK_EDEVICE;
+      ws->bhost = nullptr;
+      ws->bhost_bytes = 0;
+    }
+    if (hipHostMalloc(&ws->bhost, need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      ws->bhost = nullptr;
+      return DRTOPK_ENOMEM;
+    }
+    ws->bhost_bytes = need;
+  }
   return DRTOPK_OK;
 }
 
@@ -485,6 +557,59 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
   return after(p, ws->ptr, s);
 }
 
+// Subrange exponent of a problem taken by the batched workgroup kernel; 0 =
+// sorted outright (n <= kBSmallN) or radix select without delegates.
+int batched_alpha(uint64_t n, uint32_t k) {
+  if (n <= kBSmallN) return 0;
+  auto subranges = [n](int a) { return (n + (1ull << a) - 1) >> a; };
+  int a = -1, b = 0;
+  if (!tune_lookup(DRTOPK_FORM_BATCHED, n, k, &a, &b) || a < 0) {
+    a = rule_alpha(n, k);
+    if (a < 8) a = 8;  // a wave reads 256 keys per step: shorter subranges idle lanes
+  }
+  if (a > 24) a = 24;
+  if (a < 2) a = 2;
+  while (a < 24 && subranges(a) > kBMaxS) ++a;           // delegate vector fits the LDS
+  while (subranges(a) <= k && a > 2 && subranges(a - 1) <= kBMaxS) --a;  // more delegates than k
+  return subranges(a) > k && subranges(a) <= kBMaxS ? a : 0;
+}
+
+bool batched_eligible(uint64_t n, uint32_t k) { return n <= kBMaxN && k <= kBMaxK; }
+
+// Enqueues one k_batched launch over `items` (already validated).
+int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_t s, Workspace* ws) {
+  const size_t need = 64 + items.size() * sizeof(BatchDesc);
+  int st = ensure_batch_bytes(ws, need);
+  if (st) return st;
+  char* h = static_cast<char*>(ws->bhost);
+  std::memset(h, 0, 64);  // claim counter
+  BatchDesc* hd = reinterpret_cast<BatchDesc*>(h + 64);
+  for (size_t i = 0; i < items.size(); ++i) {
+    const drtopk_problem_t& q = *items[i];
+    BatchDesc d{};
+    d.keys = static_cast<const uint32_t*>(q.keys);
+    d.n = q.n;
+    d.k = q.k;
+    d.dtype = q.dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
+    d.alpha = (uint32_t)batched_alpha(q.n, q.k);
+    d.out_vals = static_cast<uint32_t*>(q.out_vals);
+    d.out_idx = q.out_idx;
+    d.out_kth = static_cast<uint32_t*>(q.out_kth);
+    hd[i] = d;
+  }
+  if (hipMemcpyAsync(ws->bdev, ws->bhost, need, hipMemcpyHostToDevice, s) != hipSuccess) return DRTOPK_EDEVICE;
+  if (hipEventRecord(ws->bev, s) != hipSuccess) return DRTOPK_EDEVICE;
+  ws->bev_pending = true;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned grid = (unsigned)(items.size() < (size_t)cus ? items.size() : (size_t)cus);
+  hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, s,
+                     reinterpret_cast<const BatchDesc*>(static_cast<char*>(ws->bdev) + 64), (uint32_t)items.size(),
+                     static_cast<uint32_t*>(ws->bdev));
+  if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+  return DRTOPK_OK;
+}
+
 int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   if (!stats) return DRTOPK_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
@@ -549,20 +674,69 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
     int st = check_args(q.keys, q.n, q.k, (int)q.dtype);
     if (st) return st;
   }
-  for (uint32_t i = 0; i < count; ++i) {
-    const drtopk_problem_t& q = problems[i];
-    int st;
-    try {
-      if (q.out_vals)
-        st = run_common(q.keys, q.n, q.k, (int)q.dtype, q.out_vals, q.out_idx, q.out_kth, false, nullptr, stream,
-                        [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
-      else
-        st = run_common(q.keys, q.n, q.k, (int)q.dtype, nullptr, nullptr, q.out_kth, true, nullptr, stream,
-                        [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
-    } catch (...) {
-      st = DRTOPK_EDEVICE;
+  if (count == 0) return DRTOPK_OK;
+  try {
+    // problems a workgroup can own go to one persistent launch, largest first
+    std::vector<const drtopk_problem_t*> small, large;
+    for (uint32_t i = 0; i < count; ++i)
+      (batched_eligible(problems[i].n, problems[i].k) ? small : large).push_back(&problems[i]);
+    std::stable_sort(small.begin(), small.end(),
+                     [](const drtopk_problem_t* a, const drtopk_problem_t* b) { return a->n > b->n; });
+    if (!small.empty()) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+      Workspace* ws = workspace_entry(dev, stream);
+      if (!ws) return DRTOPK_ENOMEM;
+      std::lock_guard<std::mutex> lock(ws->mu);
+      int st = launch_batched(small, reinterpret_cast<hipStream_t>(stream), ws);
+      if (st) return st;
     }
-    if (st) return st;
+    for (const drtopk_problem_t* q : large) {
+      int st = run_common(q->keys, q->n, q->k, (int)q->dtype, q->out_vals, q->out_idx, q->out_kth, !q->out_vals,
+                          nullptr, stream, [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
+      if (st) return st;
+    }
+  } catch (...) {
+    return DRTOPK_EDEVICE;
+  }
+  return DRTOPK_OK;
+}
+
+int drtopk_tune_set(const drtopk_tune_t* entries, uint32_t count) {
+  if (count && !entries) return DRTOPK_EINVAL;
+  std::vector<drtopk_tune_t> t;
+  try {
+    for (uint32_t i = 0; i < count; ++i) {
+      const drtopk_tune_t& e = entries[i];
+      if (e.form != DRTOPK_FORM_SINGLE && e.form != DRTOPK_FORM_BATCHED) return DRTOPK_EINVAL;
+      if (e.lg_n < 0 || e.lg_n > 31 || e.lg_k < 0 || e.lg_k > 31) return DRTOPK_EINVAL;
+      if (e.alpha < 0 || e.alpha > 24 || !valid_beta(e.beta)) return DRTOPK_EINVAL;
+      t.push_back(e);
+    }
+  } catch (...) {
+    return DRTOPK_ENOMEM;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.swap(t);
+  return DRTOPK_OK;
+}
+
+int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count) {
+  if (!count || (cap && !out)) return DRTOPK_EINVAL;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  *count = (uint32_t)g_tune.size();
+  for (uint32_t i = 0; i < cap && i < g_tune.size(); ++i) out[i] = g_tune[i];
+  return DRTOPK_OK;
+}
+
+int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha) {
+  if (!route || !alpha || n == 0 || n >= (1ull << 32) || k == 0 || k > n) return DRTOPK_EINVAL;
+  if (!batched_eligible(n, k)) {
+    *route = 0;
+    *alpha = 0;
+  } else {
+    *alpha = batched_alpha(n, k);
+    *route = n <= kBSmallN ? 1 : *alpha ? 2 : 3;
   }
   return DRTOPK_OK;
 }
@@ -656,9 +830,19 @@ int drtopk_release_workspace(void) {
   for (auto it = g_ws.begin(); it != g_ws.end();) {
     if (it->first.first == dev) {
       std::lock_guard<std::mutex> g2(it->second->mu);
-      if (it->second->ptr) (void)hipFree(it->second->ptr);
-      it->second->ptr = nullptr;
-      it->second->bytes = 0;
+      Workspace* w = it->second.get();
+      if (w->ptr) (void)hipFree(w->ptr);
+      w->ptr = nullptr;
+      w->bytes = 0;
+      if (w->bdev) (void)hipFree(w->bdev);
+      w->bdev = nullptr;
+      w->bdev_bytes = 0;
+      if (w->bhost) (void)hipHostFree(w->bhost);
+      w->bhost = nullptr;
+      w->bhost_bytes = 0;
+      if (w->bev) (void)hipEventDestroy(w->bev);
+      w->bev = nullptr;
+      w->bev_pending = false;
       ++it;
     } else {
       ++it;

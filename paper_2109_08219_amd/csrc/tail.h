@@ -316,15 +316,16 @@ __device__ __forceinline__ void bs_stage(uint64_t (&v)[E], uint64_t* lds) {
   if constexpr (J > 1) bs_stage<E, S, J / 2>(v, lds);
 }
 
-template <int E, uint32_t S>
+template <int E, uint32_t S, int NT>
 __device__ __forceinline__ void bs_size(uint64_t (&v)[E], uint64_t* lds) {
   bs_stage<E, S, S / 2>(v, lds);
-  if constexpr (S < (uint32_t)E * kTailThreads) bs_size<E, S * 2>(v, lds);
+  if constexpr (S < (uint32_t)E * NT) bs_size<E, S * 2, NT>(v, lds);
 }
 
-template <int E>
+// Sorts the E * NT composites held E per thread by a block of NT threads.
+template <int E, int NT = kTailThreads>
 __device__ __forceinline__ void block_bitonic(uint64_t (&v)[E], uint64_t* lds) {
-  bs_size<E, 2>(v, lds);
+  bs_size<E, 2, NT>(v, lds);
   __syncthreads();
 }
 

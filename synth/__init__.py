@@ -167,3 +167,22 @@ def keys(kind: str, n: int, seed: int = DEFAULT_SEED) -> tuple[np.ndarray, str]:
     if kind == "heavydup_u32":
         return heavy_dup_u32(n, seed), "u32"
     raise ValueError(f"unknown workload kind {kind!r}")
+
+
+def batched_workload(count: int, seed: int = DEFAULT_SEED, lo_exp: int = 10, hi_exp: int = 20,
+                     k_cap: int = 2048) -> list[tuple[str, int, int, int]]:
+    """Independent instances for the batched form: (kind, n, k, seed) each.
+
+    Lengths are log-uniform in [2^lo_exp, 2^hi_exp]; each instance is uint32
+    uniform or float32 standard normal (a fair coin from its own seed); k is
+    uniform in [1, min(n, k_cap)]."""
+    ns = log_uniform_int(count, lo_exp, hi_exp, derive_seed(seed, 1))
+    coin = unit_uniform(count, derive_seed(seed, 2))
+    ku = unit_uniform(count, derive_seed(seed, 3))
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        kind = "uniform_u32" if coin[i] < 0.5 else "normal_f32"
+        k = 1 + int(ku[i] * min(n, k_cap))
+        out.append((kind, n, k, derive_seed(seed, 1000 + i)))
+    return out

@@ -67,3 +67,55 @@ def test_batched_validates_every_problem_first():
     assert L.topk_select_batched(probs, 2, None) == 1
     assert L.topk_select_batched(None, 1, None) == 1
     assert L.topk_select_batched(None, 0, None) == 0
+
+
+def test_tune_table_roundtrip_and_validation():
+    saved = drt.tune_get()
+    try:
+        drt.tune_set([])
+        assert drt.tune_get() == []
+        entries = [(drt.FORM_SINGLE, 30, 10, 12, 1), (drt.FORM_BATCHED, 16, 5, 9, 1)]
+        drt.tune_set(entries)
+        assert drt.tune_get() == entries
+        # form-0 entries steer the planner, explicit options aside
+        assert drt.plan(2 ** 30, 1024) == drt.Plan(1, 12, 1)
+        assert drt.plan(2 ** 30, 2047) == drt.Plan(1, 12, 1)  # same floor(log2 k)
+        assert drt.plan(2 ** 30, 2048) == drt.Plan(1, 11, 1)  # no entry: Rule 4
+        L = drt.lib()
+        for bad in [(2, 16, 5, 9, 1), (0, 16, 5, 25, 1), (0, 16, 5, 9, 3), (0, -1, 5, 9, 1), (1, 16, 32, 9, 1)]:
+            arr = (drt.Tune * 1)(drt.Tune(*bad))
+            assert L.drtopk_tune_set(arr, 1) == 1, bad
+        assert drt.tune_get() == entries  # a rejected table leaves the old one
+        assert L.drtopk_tune_set(None, 1) == 1
+        assert L.drtopk_tune_get(None, 0, None) == 1
+    finally:
+        drt.tune_set(saved)
+
+
+def test_batched_routes_without_gpu():
+    saved = drt.tune_get()
+    try:
+        drt.tune_set([])
+        assert drt.batched_route(1, 1) == (1, 0)
+        assert drt.batched_route(8192, 2048) == (1, 0)
+        for n in (8193, 65541, 1 << 20, 1 << 22):
+            for k in (1, 7, 1024, 2048):
+                r, a = drt.batched_route(n, k)
+                S = -(-n // (1 << a))
+                assert r == 2 and 2 <= a <= 24 and k < S <= 4096, (n, k, r, a)
+        assert drt.batched_route(1 << 20, 1) == (2, 11)  # Rule 4: floor((20 - 0 + 3) / 2)
+        assert drt.batched_route(1 << 22, 2048) == (2, 10)  # Rule 4 gives 7: raised until S <= 4096
+        assert drt.batched_route((1 << 22) + 1, 1) == (0, 0)
+        assert drt.batched_route(1 << 20, 2049) == (0, 0)
+        drt.tune_set([(drt.FORM_BATCHED, 16, 2, 3, 1)])
+        assert drt.batched_route(1 << 16, 5) == (2, 4)  # raised until S <= 4096
+        drt.tune_set([(drt.FORM_BATCHED, 16, 10, 16, 1)])
+        r, a = drt.batched_route(1 << 16, 1024)
+        assert r == 2 and -(-(1 << 16) // (1 << a)) > 1024  # lowered until S > k
+        L = drt.lib()
+        r, al = ctypes.c_int32(), ctypes.c_int32()
+        assert L.drtopk_batched_alpha(0, 1, ctypes.byref(r), ctypes.byref(al)) == 1
+        assert L.drtopk_batched_alpha(10, 11, ctypes.byref(r), ctypes.byref(al)) == 1
+        assert L.drtopk_batched_alpha(10, 1, None, ctypes.byref(al)) == 1
+    finally:
+        drt.tune_set(saved)

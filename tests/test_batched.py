@@ -1,0 +1,188 @@
+"""Batched form vs the oracle and vs the single-problem path, through the C-ABI.
+
+Every batched problem must equal the oracle's answer for it and, bit for bit,
+what topk_select / kth_select give for the same problem alone.  The cases
+reach each route a problem can take in the persistent kernel (sorted
+outright, delegate method in LDS, radix select when the survivors overflow)
+and the single-problem path for problems too large for one workgroup.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from checks import check_exact, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+drt = pytest.importorskip("paper_2109_08219_amd")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(autouse=True)
+def default_tuning():
+    """Each test starts and ends with the table the binding loads by default."""
+    saved = drt.tune_get()
+    yield
+    drt.tune_set(saved)
+
+
+def run_batch(hosts, *, kth_only=False, offsets=None):
+    """hosts: list of (x, dtype, k).  Returns the Batch after it ran."""
+    tensors = []
+    for i, (x, dt, k) in enumerate(hosts):
+        off = offsets[i] if offsets else 0
+        t = dev(np.concatenate([np.zeros(off, dtype=x.dtype), x]))[off:] if off else dev(x)
+        tensors.append((t, k))
+    b = drt.Batch(tensors, kth_only=kth_only)
+    b.run()
+    torch.cuda.synchronize()
+    return b
+
+
+def check_batch(hosts, b, what):
+    for i, (x, dt, k) in enumerate(hosts):
+        kth = to_np(b.kth_value(i)).view(np.uint32)[0]
+        want_kth = np.asarray(oracle.kth_value(x, k, dt)).view(np.uint32)
+        assert kth == want_kth, (what, i, x.shape[0], k)
+        if not b.kth_only:
+            check_exact(x, k, dt, to_np(b.values(i)), to_np(b.indices(i)), f"{what} #{i} n={x.shape[0]} k={k}")
+
+
+def workload_hosts(count, seed):
+    hosts = []
+    for kind, n, k, s in synth.batched_workload(count, seed):
+        x, dt = synth.keys(kind, n, s)
+        hosts.append((x, dt, k))
+    return hosts
+
+
+def test_routes_are_planned():
+    assert drt.batched_route(8192, 100) == (1, 0)
+    r, a = drt.batched_route(1 << 20, 1024)
+    assert r == 2 and a >= 8 and -(-(1 << 20) // (1 << a)) <= 4096
+    assert drt.batched_route((1 << 22) + 1, 10)[0] == 0
+    assert drt.batched_route(1 << 16, 2049)[0] == 0
+
+
+def test_workload_sample_exact():
+    """The batched workload recipe (lengths log-uniform in [2^10, 2^20], k <= 2048,
+    uint32 uniform or float32 normal per instance) on 256 instances."""
+    hosts = workload_hosts(256, 4242)
+    say("workload 256")
+    b = run_batch(hosts)
+    check_batch(hosts, b, "workload")
+
+
+def test_each_route():
+    hosts = []
+    # sorted outright in the workgroup
+    for n, k in [(1, 1), (2, 2), (3, 1), (100, 37), (1000, 1000), (4096, 2048), (4097, 5), (8192, 2048)]:
+        for kind in ("uniform_u32", "normal_f32", "heavydup_u32"):
+            x, dt = synth.keys(kind, n, 31 + n)
+            hosts.append((x, dt, k))
+    # delegate method in LDS, ragged last subrange
+    for n, k in [(8193, 1), (8193, 2048), (65541, 1), (65541, 7), (65541, 2048), ((1 << 20) + 5, 1000),
+                 ((1 << 22), 2048), ((1 << 22) - 3, 1)]:
+        for kind in ("uniform_u32", "normal_f32"):
+            x, dt = synth.keys(kind, n, 57 + n)
+            assert drt.batched_route(n, k)[0] == 2
+            hosts.append((x, dt, k))
+    # survivors overflow the workgroup: ascending input and 16 distinct values
+    for n, k in [(1 << 18, 2000), (100003, 64), (1 << 20, 2048)]:
+        for kind in ("sorted_f32", "heavydup_u32"):
+            x, dt = synth.keys(kind, n, 91 + n)
+            hosts.append((x, dt, k))
+    say("routes", len(hosts))
+    b = run_batch(hosts)
+    check_batch(hosts, b, "routes")
+
+
+@pytest.mark.parametrize("alpha", [2, 3, 5, 8, 9, 11, 13, 16])
+def test_tuned_alpha_is_exact(alpha):
+    """Any table entry gives the same (exact) results: the kernel only raises
+    alpha to fit its delegate vector or lowers it to keep more delegates than k."""
+    hosts = []
+    for i, (n, k) in enumerate([(9000, 1), (9000, 1500), (40000, 33), (200000, 2048), (600001, 300),
+                                ((1 << 20) + 1, 2000)]):
+        x, dt = synth.keys("normal_f32" if i % 2 else "uniform_u32", n, 300 + i)
+        hosts.append((x, dt, k))
+    entries = []
+    for x, dt, k in hosts:
+        lg_n, lg_k = int(np.log2(x.shape[0])), int(np.log2(k))
+        entries.append((drt.FORM_BATCHED, lg_n, lg_k, alpha, 1))
+    drt.tune_set(entries)
+    say("tuned alpha", alpha)
+    b = run_batch(hosts)
+    check_batch(hosts, b, f"alpha {alpha}")
+
+
+def test_batched_equals_single_bitwise():
+    hosts = workload_hosts(64, 777)
+    big = [(synth.keys("uniform_u32", (1 << 22) + 1, 5)[0], "u32", 100),
+           (synth.keys("normal_f32", 1 << 16, 6)[0], "f32", 3000)]
+    hosts = hosts[:32] + big + hosts[32:]
+    say("batched vs single", len(hosts))
+    b = run_batch(hosts)
+    for i, (x, dt, k) in enumerate(hosts):
+        t = dev(x)
+        v, ix = drt.topk_select(t, k)
+        kth = drt.kth_select(t, k)
+        torch.cuda.synchronize()
+        assert (to_np(b.values(i)).view(np.uint32) == to_np(v).view(np.uint32)).all(), i
+        assert (to_np(b.indices(i)) == to_np(ix)).all(), i
+        assert to_np(b.kth_value(i)).view(np.uint32)[0] == to_np(kth).view(np.uint32)[0], i
+    check_batch(hosts, b, "mixed")
+
+
+def test_kth_only_and_unaligned():
+    hosts = workload_hosts(48, 99)
+    say("kth only")
+    b = run_batch(hosts, kth_only=True)
+    check_batch(hosts, b, "kth only")
+    say("unaligned")
+    b = run_batch(hosts, offsets=[1 + (i % 3) for i in range(len(hosts))])
+    check_batch(hosts, b, "unaligned")
+
+
+def test_repeat_reuse_and_side_stream():
+    hosts = workload_hosts(40, 123)
+    tensors = [(dev(x), k) for x, _, k in hosts]
+    b = drt.Batch(tensors)
+    small = drt.Batch(tensors[:5])
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        say("repeat", rep)
+        b.vals.fill_(0)
+        with torch.cuda.stream(s):
+            b.run(stream=s)
+            small.run(stream=s)
+        s.synchronize()
+        check_batch(hosts, b, f"repeat {rep}")
+        check_batch(hosts[:5], small, f"repeat small {rep}")
+
+
+def test_errors():
+    t = dev(synth.uniform_u32(100, 1))
+    with pytest.raises(drt.DrTopkError):
+        drt.topk_select_batched([(t, 5), (t, 101)])
+    with pytest.raises(TypeError):
+        drt.topk_select_batched([(t.view(torch.int32), 5)])
+
+
+def test_full_workload_4096():
+    """The full batched workload: 4096 instances, every one checked exactly."""
+    hosts = workload_hosts(4096, synth.DEFAULT_SEED)
+    say("full 4096")
+    b = run_batch(hosts)
+    check_batch(hosts, b, "full")
