@@ -195,6 +195,62 @@ int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out);
 int drtopk_timing_enable(int on);
 int drtopk_timing_read(double* delegate_ms, double* tail_ms, uint64_t* calls);
 
+/* HBM bytes a problem occupies while it is in flight: its input (4n), its
+ * outputs (8k + 4) and the workspace of the route it takes.  The serving loop
+ * admits requests by this figure.  DRTOPK_EINVAL for arguments topk_select
+ * would reject. */
+int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes);
+
+/* Serving loop: continuous batching of requests over device-resident arrays
+ * (each request is a drtopk_problem_t: device pointers, the caller keeps them
+ * alive until the request completes).  A server owns `streams` launch streams
+ * and one dispatcher thread.  Whenever a stream is free, the dispatcher admits
+ * queued requests in arrival order while the summed footprint of admitted,
+ * unfinished requests stays within hbm_budget (a request larger than the
+ * budget is admitted alone), at most max_batch per launch, and launches them
+ * together with topk_select_batched on that stream.  Requests arriving while
+ * launches run join the next launch, so their work overlaps on the device.
+ * Results are bit-identical to topk_select / kth_select on each request
+ * alone.  plain = 1 turns the server into the per-request baseline: one
+ * topk_select (or kth_select) call per request, in arrival order.
+ * The device is the caller's current device at creation.  A server keeps a
+ * record (about 100 bytes) of every request it has served until destroyed. */
+typedef struct drtopk_server drtopk_server_t;
+typedef struct {
+  uint64_t hbm_budget; /* bytes; 0 = 8 GiB */
+  uint32_t max_batch;  /* >= 1 */
+  uint32_t streams;    /* 1..16, default priority */
+  uint32_t plain;      /* 0 batched server, 1 per-request baseline */
+  uint32_t reserved;   /* 0 */
+} drtopk_server_config_t;
+typedef struct {
+  uint64_t completed;          /* latencies recorded since the last reset */
+  uint64_t launches;           /* launches since the last reset */
+  uint64_t launched_items;     /* requests in those launches */
+  uint64_t max_inflight_bytes; /* peak admitted footprint */
+  double mean_us, p50_us, p99_us, max_us; /* arrival -> completion seen by the host */
+} drtopk_server_stats_t;
+int drtopk_server_create(const drtopk_server_config_t* cfg, drtopk_server_t** out);
+/* Queues one request (arrival = now); *ticket identifies it. */
+int drtopk_server_submit(drtopk_server_t* server, const drtopk_problem_t* req, uint64_t* ticket);
+/* Blocks until the request completes; returns its status and, if non-NULL,
+ * its latency in microseconds. */
+int drtopk_server_wait(drtopk_server_t* server, uint64_t ticket, double* latency_us);
+/* Blocks until every submitted request has completed; returns the first
+ * failure status among requests completed since the previous drain, else OK. */
+int drtopk_server_drain(drtopk_server_t* server);
+/* Latency percentiles (nearest rank) over requests completed since the last
+ * reset; reset != 0 starts a new window. */
+int drtopk_server_stats(drtopk_server_t* server, drtopk_server_stats_t* out, int reset);
+/* Open-loop load: submits reqs[i] at arrival_us[i] (non-decreasing, from the
+ * call's start) from the calling thread, waits for all, and writes each
+ * request's latency (from its scheduled arrival) to latency_us[i] and the
+ * wall time of the whole replay to *elapsed_us (either may be NULL). */
+int drtopk_server_replay(drtopk_server_t* server, const drtopk_problem_t* reqs, const double* arrival_us,
+                         uint32_t count, double* latency_us, double* elapsed_us);
+/* Finishes queued work, stops the dispatcher and frees the server. */
+int drtopk_server_destroy(drtopk_server_t* server);
+
 /* Frees the calling thread's current device's workspaces (synchronises it). */
 int drtopk_release_workspace(void);
 

@@ -54,6 +54,17 @@ class Problem(ctypes.Structure):
                 ("out_kth", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("plain", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("launched_items", ctypes.c_uint64),
+                ("max_inflight_bytes", ctypes.c_uint64), ("mean_us", ctypes.c_double), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("max_us", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -82,6 +93,15 @@ def lib() -> ctypes.CDLL:
             "drtopk_tune_set": [ctypes.POINTER(Tune), u32],
             "drtopk_tune_get": [ctypes.POINTER(Tune), u32, ctypes.POINTER(u32)],
             "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+            "drtopk_footprint": [u64, u32, i32, ctypes.POINTER(u64)],
+            "drtopk_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
+            "drtopk_server_submit": [vp, ctypes.POINTER(Problem), ctypes.POINTER(u64)],
+            "drtopk_server_wait": [vp, u64, ctypes.POINTER(ctypes.c_double)],
+            "drtopk_server_drain": [vp],
+            "drtopk_server_stats": [vp, ctypes.POINTER(ServerStats), i32],
+            "drtopk_server_replay": [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_double), u32,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+            "drtopk_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -332,6 +352,76 @@ def batched_route(n: int, k: int) -> tuple[int, int]:
     r, a = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().drtopk_batched_alpha(n, k, ctypes.byref(r), ctypes.byref(a)), "drtopk_batched_alpha")
     return r.value, a.value
+
+
+def footprint(n: int, k: int, dtype: str = "u32") -> int:
+    """HBM bytes a problem occupies while in flight (input, outputs, workspace)."""
+    b = ctypes.c_uint64()
+    _check(lib().drtopk_footprint(n, k, {"u32": U32, "f32": F32}[dtype], ctypes.byref(b)), "drtopk_footprint")
+    return b.value
+
+
+class Server:
+    """Continuous-batching server over device-resident arrays (see drtopk_server_* in the C header).
+
+    Requests are (keys, k) pairs or a Batch of them; results land in the Batch's packed outputs."""
+
+    def __init__(self, *, hbm_budget: int = 0, max_batch: int = 256, streams: int = 4, plain: bool = False):
+        cfg = ServerConfig(hbm_budget, max_batch, streams, 1 if plain else 0, 0)
+        h = ctypes.c_void_p()
+        _check(lib().drtopk_server_create(ctypes.byref(cfg), ctypes.byref(h)), "drtopk_server_create")
+        self._h = h
+
+    def replay(self, batch: "Batch", arrival_us):
+        """Submits batch problem i at arrival_us[i] (microseconds from now); returns
+        (latencies_us list, elapsed_us)."""
+        import numpy as np
+        arr = np.ascontiguousarray(np.asarray(arrival_us, dtype=np.float64))
+        if arr.shape[0] != batch.count:
+            raise ValueError("one arrival time per problem")
+        lat = np.zeros(max(1, batch.count), dtype=np.float64)
+        el = ctypes.c_double()
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = lib().drtopk_server_replay(self._h, batch._descs, arr.ctypes.data_as(dp), batch.count,
+                                        lat.ctypes.data_as(dp), ctypes.byref(el))
+        _check(rc, "drtopk_server_replay")
+        return lat[:batch.count], el.value
+
+    def submit(self, batch: "Batch", i: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().drtopk_server_submit(self._h, ctypes.byref(batch._descs[i]), ctypes.byref(t)),
+               "drtopk_server_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        _check(lib().drtopk_server_wait(self._h, ticket, ctypes.byref(lat)), "drtopk_server_wait")
+        return lat.value
+
+    def drain(self) -> None:
+        _check(lib().drtopk_server_drain(self._h), "drtopk_server_drain")
+
+    def stats(self, reset: bool = False) -> ServerStats:
+        st = ServerStats()
+        _check(lib().drtopk_server_stats(self._h, ctypes.byref(st), 1 if reset else 0), "drtopk_server_stats")
+        return st
+
+    def close(self) -> None:
+        if self._h:
+            h, self._h = self._h, None
+            _check(lib().drtopk_server_destroy(h), "drtopk_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_workspace() -> None:

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdrtopk.so")
-SOURCES = [os.path.join(HERE, "csrc", "drtopk.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "drtopk.hip"), os.path.join(HERE, "csrc", "server.cpp")]
 HEADERS = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc")) if f.endswith(".h"))
 HEADERS.append(os.path.join(ROOT, "include", "drtopk.h"))
 

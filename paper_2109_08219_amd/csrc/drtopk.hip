@@ -702,6 +702,22 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
   return DRTOPK_OK;
 }
 
+int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes) {
+  if (!bytes) return DRTOPK_EINVAL;
+  alignas(16) static const uint32_t dummy[4] = {0, 0, 0, 0};
+  int st = check_args(dummy, n, k, dtype);
+  if (st) return st;
+  uint64_t ws = sizeof(BatchDesc);
+  if (!batched_eligible(n, k)) {
+    Plan p;
+    st = make_plan(dummy, n, k, dtype, nullptr, &p);
+    if (st) return st;
+    ws = p.total;
+  }
+  *bytes = 4 * n + 8ull * k + 4 + ws;
+  return DRTOPK_OK;
+}
+
 int drtopk_tune_set(const drtopk_tune_t* entries, uint32_t count) {
   if (count && !entries) return DRTOPK_EINVAL;
   std::vector<drtopk_tune_t> t;

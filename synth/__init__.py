@@ -186,3 +186,23 @@ def batched_workload(count: int, seed: int = DEFAULT_SEED, lo_exp: int = 10, hi_
         k = 1 + int(ku[i] * min(n, k_cap))
         out.append((kind, n, k, derive_seed(seed, 1000 + i)))
     return out
+
+
+def serving_workload(count: int, seed: int = DEFAULT_SEED, lo_exp: int = 12, hi_exp: int = 26,
+                     k_hi_exp: int = 12) -> list[tuple[str, int, int]]:
+    """Requests of the serving workload: (kind, n, k) each.  n is log-uniform in
+    [2^lo_exp, 2^hi_exp]; the keys are uint32 uniform or float32 standard normal
+    (a fair coin); k is log-uniform in [1, 2^k_hi_exp], capped at n."""
+    ns = log_uniform_int(count, lo_exp, hi_exp, derive_seed(seed, 11))
+    coin = unit_uniform(count, derive_seed(seed, 12))
+    ks = log_uniform_int(count, 0, k_hi_exp, derive_seed(seed, 13))
+    return [("uniform_u32" if coin[i] < 0.5 else "normal_f32", int(ns[i]), int(min(ks[i], ns[i])))
+            for i in range(count)]
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """Arrival times in microseconds of a Poisson process: cumulative sums of
+    exponential gaps -ln(1 - u) / rate."""
+    u = unit_uniform(count, derive_seed(seed, 21))
+    gaps = -np.log1p(-u) / rate_per_s * 1e6
+    return np.cumsum(gaps)

@@ -119,3 +119,24 @@ def test_batched_routes_without_gpu():
         assert L.drtopk_batched_alpha(10, 1, None, ctypes.byref(al)) == 1
     finally:
         drt.tune_set(saved)
+
+
+def test_server_and_footprint_arguments_without_gpu():
+    L = drt.lib()
+    h = ctypes.c_void_p()
+    for bad in [(0, 0, 1, 0), (0, 1, 0, 0), (0, 1, 17, 0), (0, 1, 1, 2)]:
+        cfg = drt.ServerConfig(bad[0], bad[1], bad[2], bad[3], 0)
+        assert L.drtopk_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1, bad
+    assert L.drtopk_server_create(None, ctypes.byref(h)) == 1
+    t = ctypes.c_uint64()
+    p = drt.Problem(16, 10, 1, 0, 32, 0, 0)
+    assert L.drtopk_server_submit(None, ctypes.byref(p), ctypes.byref(t)) == 1
+    assert L.drtopk_server_wait(None, 0, None) == 1
+    assert L.drtopk_server_drain(None) == 1
+    assert L.drtopk_server_destroy(None) == 1
+    # footprint: input + outputs + workspace of the route
+    assert drt.footprint(1000, 10) == 4000 + 84 + 64
+    assert drt.footprint(1 << 24, 100) > 4 * (1 << 24) + 804
+    b = ctypes.c_uint64()
+    assert L.drtopk_footprint(10, 11, 0, ctypes.byref(b)) == 1
+    assert L.drtopk_footprint(10, 1, 0, None) == 1

@@ -1,0 +1,119 @@
+"""Serving loop: every request's result is the same alone and in the mix.
+
+Requests follow the serving workload (n log-uniform, uint32 uniform or float32
+normal, k log-uniform up to 4096) at smaller sizes, arrive as a Poisson stream
+fast enough that launches overlap on several streams, and are compared bit for
+bit with topk_select / kth_select on each request alone, and a sample with
+the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from checks import check_exact, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+drt = pytest.importorskip("paper_2109_08219_amd")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def make_requests(count, seed, hi_exp=22):
+    hosts, tensors = [], []
+    for i, (kind, n, k) in enumerate(synth.serving_workload(count, seed, hi_exp=hi_exp)):
+        x, dt = synth.keys(kind, n, synth.derive_seed(seed, 5000 + i))
+        hosts.append((x, dt, k))
+        tensors.append((torch.from_numpy(x).cuda(), k))
+    return hosts, tensors
+
+
+def alone(tensors):
+    res = []
+    for t, k in tensors:
+        v, ix = drt.topk_select(t, k)
+        kth = drt.kth_select(t, k)
+        res.append((to_np(v).view(np.uint32), to_np(ix), to_np(kth).view(np.uint32)[0]))
+    torch.cuda.synchronize()
+    return res
+
+
+def assert_same(b, ref, what):
+    for i, (v, ix, kth) in enumerate(ref):
+        assert (to_np(b.values(i)).view(np.uint32) == v).all(), (what, i)
+        assert (to_np(b.indices(i)) == ix).all(), (what, i)
+        assert to_np(b.kth_value(i)).view(np.uint32)[0] == kth, (what, i)
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    hosts, tensors = make_requests(300, 2024)
+    # a few requests too large for one workgroup take the single-problem path inside the mix
+    for j, n in enumerate(((1 << 23) + 7, (1 << 24) - 5)):
+        x, dt = synth.keys("normal_f32" if j else "uniform_u32", n, 77 + j)
+        hosts.insert(50 + 100 * j, (x, dt, 3000))
+        tensors.insert(50 + 100 * j, (torch.from_numpy(x).cuda(), 3000))
+    return hosts, tensors, alone(tensors)
+
+
+@pytest.mark.parametrize("streams,max_batch", [(4, 64), (1, 8), (8, 256)])
+def test_alone_equals_mix(reqs, streams, max_batch):
+    hosts, tensors, ref = reqs
+    b = drt.Batch(tensors)
+    arr = synth.poisson_arrivals(len(tensors), 40000.0, 9)
+    say("serving mix", streams, max_batch)
+    with drt.Server(streams=streams, max_batch=max_batch) as srv:
+        lat, el = srv.replay(b, arr)
+        st = srv.stats()
+    torch.cuda.synchronize()
+    say("  launches", st.launches, "items", st.launched_items, "p50", round(st.p50_us, 1), "p99", round(st.p99_us, 1))
+    assert st.completed == len(tensors) and st.launched_items == len(tensors)
+    assert st.launches <= len(tensors)
+    assert (lat > 0).all()
+    assert_same(b, ref, f"mix {streams} {max_batch}")
+    for i in range(0, len(hosts), 37):
+        x, dt, k = hosts[i]
+        check_exact(x, k, dt, to_np(b.values(i)), to_np(b.indices(i)), f"serving #{i}")
+
+
+def test_plain_baseline_same(reqs):
+    hosts, tensors, ref = reqs
+    b = drt.Batch(tensors)
+    arr = synth.poisson_arrivals(len(tensors), 20000.0, 10)
+    say("plain server")
+    with drt.Server(streams=1, max_batch=1, plain=True) as srv:
+        srv.replay(b, arr)
+        st = srv.stats()
+    assert st.launches == len(tensors)
+    assert_same(b, ref, "plain")
+
+
+def test_admission_budget(reqs):
+    hosts, tensors, ref = reqs
+    fps = [drt.footprint(t.numel(), k, "f32" if t.dtype == torch.float32 else "u32") for t, k in tensors]
+    budget = 3 * int(np.median(fps))
+    b = drt.Batch(tensors)
+    say("admission budget", budget)
+    with drt.Server(streams=4, max_batch=64, hbm_budget=budget) as srv:
+        srv.replay(b, np.zeros(len(tensors)))
+        st = srv.stats()
+    assert st.max_inflight_bytes <= max(budget, max(fps))
+    assert_same(b, ref, "budget")
+
+
+def test_submit_wait_kth_only(reqs):
+    hosts, tensors, ref = reqs
+    b = drt.Batch(tensors[:40], kth_only=True)
+    with drt.Server(streams=2, max_batch=16) as srv:
+        tickets = [srv.submit(b, i) for i in range(b.count)]
+        lats = [srv.wait(t) for t in tickets]
+        srv.drain()
+    assert all(l > 0 for l in lats)
+    for i in range(b.count):
+        assert to_np(b.kth_value(i)).view(np.uint32)[0] == ref[i][2], i
