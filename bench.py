@@ -9,9 +9,20 @@ k in {1, 1024, 131072}: six topk_select calls, sorted values + positions.
 Reported: keys/s over the whole step (value), HBM GB/s of the mandatory read
 (4 bytes per key), per-case timings, the roofline of the dominant kernel (the
 delegate pass, timed live with HIP events on its own stream), and the CPU
-oracle on a bounded sample of the same workload.
+oracle on a bounded sample of the same workload.  Beside the step, outside
+its timed region:
+  batched  4096 independent instances (lengths log-uniform in [2^10, 2^20],
+           uint32 uniform or float32 normal per instance, k uniform in
+           [1, min(n, 2048)]) in one topk_select_batched call, queries/s,
+           against a loop of topk_select over the same instances;
+  serving  Poisson arrivals of requests over a device-resident pool of arrays
+           (n log-uniform in [2^12, 2^26], uint32 uniform / float32 normal,
+           k log-uniform in [1, 4096]): the continuous-batching server and the
+           per-request loop at 0.8x and 1.5x the loop's saturation rate,
+           queries/s and p50/p99 latency (arrival -> completion on the host).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-batched] [--no-serving]
 """
 from __future__ import annotations
 
@@ -55,12 +66,87 @@ def traffic_for_current_kernel():
     return t.get("hbm_bytes_per_launch")
 
 
+def _gpu_keys(torch, kind, n, gen):
+    if kind == "uniform_u32":
+        return torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=gen).view(torch.uint32)
+    return torch.randn(n, device="cuda", generator=gen)
+
+
+def bench_batched(drt, synth, torch, args):
+    """4096 instances in one batched call vs a loop of topk_select over them."""
+    print("[bench] batched: generating 4096 instances", file=sys.stderr, flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.DEFAULT_SEED)
+    probs = [(_gpu_keys(torch, kind, n, gen), k) for kind, n, k, _ in synth.batched_workload(4096)]
+    total = sum(t.numel() for t, _ in probs)
+    b = drt.Batch(probs)
+    for _ in range(max(1, args.warmup)):
+        b.run()
+    torch.cuda.synchronize()
+    steps = max(5, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    print("[bench] batched: per-query loop", file=sys.stderr, flush=True)
+    outs = [(torch.empty(k, dtype=t.dtype, device="cuda"), torch.empty(k, dtype=torch.int32, device="cuda"))
+            for t, k in probs]
+    for (t, k), (v, ix) in zip(probs, outs):
+        drt.topk_select(t, k, v, ix)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (t, k), (v, ix) in zip(probs, outs):
+        drt.topk_select(t, k, v, ix)
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t0) * 1e3
+    return {"instances": len(probs), "keys": total, "ms_per_batch": ms, "queries_per_s": len(probs) / ms * 1e3,
+            "GBps": 4.0 * total / ms / 1e6, "loop_ms": ms_loop, "loop_queries_per_s": len(probs) / ms_loop * 1e3,
+            "speedup_vs_loop": ms_loop / ms, "steps": steps}
+
+
+def bench_serving(drt, synth, torch, np, pool_size=256, requests=4000):
+    """Continuous-batching server vs the per-request loop under Poisson arrivals."""
+    print("[bench] serving: building the array pool", file=sys.stderr, flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.DEFAULT_SEED + 1)
+    pool = [_gpu_keys(torch, kind, n, gen) for kind, n, _ in synth.serving_workload(pool_size, 99)]
+    pick = (synth.unit_uniform(requests, 5) * pool_size).astype(np.int64)
+    ks = synth.log_uniform_int(requests, 0, 12, 6)
+    reqs = [(pool[i], int(min(k, pool[i].numel()))) for i, k in zip(pick, ks)]
+    b = drt.Batch(reqs)
+    torch.cuda.synchronize()
+
+    def run(plain, arrivals):
+        with drt.Server(streams=1 if plain else 4, max_batch=1 if plain else 256, plain=plain) as srv:
+            lat, el = srv.replay(b, arrivals)
+            st = srv.stats()
+        return {"queries_per_s": requests / el * 1e6, "p50_us": float(np.percentile(lat, 50)),
+                "p99_us": float(np.percentile(lat, 99)), "mean_batch": st.launched_items / max(1, st.launches)}
+
+    burst = np.zeros(requests)
+    run(True, burst)  # warm both paths
+    run(False, burst)
+    mu_loop = run(True, burst)["queries_per_s"]
+    res = {"requests": requests, "pool_arrays": pool_size,
+           "pool_GiB": sum(t.numel() for t in pool) * 4 / 2 ** 30, "loop_saturation_qps": mu_loop,
+           "server_saturation_qps": run(False, burst)["queries_per_s"], "rates": []}
+    for f in (0.8, 1.5):
+        print(f"[bench] serving: lambda = {f} x loop saturation", file=sys.stderr, flush=True)
+        arr = synth.poisson_arrivals(requests, f * mu_loop, 3)
+        res["rates"].append({"lambda_qps": f * mu_loop, "per_request_loop": run(True, arr),
+                             "batched_server": run(False, arr)})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,6 +241,12 @@ def main() -> int:
                "sample": f"the first 2^26 keys of each input, the same six (dtype, k) calls; "
                          f"numpy selection oracle (single-threaded partition + sort), {t_cpu:.1f} s"}
 
+    case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
+    del cases, t_u, t_f
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else bench_batched(drt, synth, torch, args)
+    serving = None if args.no_serving else bench_serving(drt, synth, torch, np)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -178,9 +270,11 @@ def main() -> int:
                      "avg_launch_us": del_avg_s * 1e6, "launches": calls,
                      "rest_of_path_avg_us": tail_ms / calls * 1e3},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
         "cases": [{k: c[k] for k in ("dtype", "k", "alpha", "beta", "scanned", "candidates", "ms_median", "ms_min")}
                   | {"keys_per_s": N / (c["ms_median"] / 1e3), "GBps": 4 * N / (c["ms_median"] / 1e3) / 1e9}
-                  for c in cases],
+                  for c in case_rows],
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -118,14 +118,16 @@ int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count);
  *          2 = delegate method in the workgroup with subrange exponent
  *          *alpha, 3 = workgroup radix select without delegates.
  * Route 2 falls back to route 3 on the device when the survivors of an
- * input exceed the workgroup's capacity (8192). */
+ * input exceed the workgroup's capacity (4096). */
 int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha);
 
 /* Explicit method parameters (for tests, tuning and ablations).
  *   alpha  subrange = 2^alpha elements (Section 5.1); -1 = planner's choice
  *   beta   delegates per subrange (Rule 3): 1, 2, 4 or 8; 0 = planner's choice
  *   mode   0 = planner's choice, 1 = delegate method, 2 = plain radix select
- *          over V with no delegates
+ *          over V with no delegates, 3 = the whole problem in one workgroup
+ *          (the batched form's kernel, one launch; n <= 2^22, k <= 2048; the
+ *          planner takes it for n <= 2^17; alpha is then the batched form's)
  *   variant  implementation of the steps after the delegate pass: 0 = one
  *          cooperative kernel (default), 1 = one kernel per step.  Both give
  *          bit-identical results. */
@@ -139,7 +141,8 @@ typedef struct {
 /* Counters of one call (host struct, filled after the call's work finishes;
  * passing non-NULL makes the call synchronise `stream`). */
 typedef struct {
-  int32_t mode;          /* 1 delegate method, 2 plain radix select */
+  int32_t mode;          /* 1 delegate method, 2 plain radix select, 3 one workgroup
+                            (then only alpha, beta, subranges, delegates are set) */
   int32_t alpha, beta;
   uint64_t subranges;    /* S = ceil(n / 2^alpha) */
   uint64_t delegates;    /* |D| = S * beta */

@@ -32,7 +32,7 @@ namespace {
 constexpr double kAlphaConst = 3.0;  // Rule 4's const; the paper tuned it to 3
 
 struct Plan {
-  int mode = 0;  // 1 delegate method, 2 plain radix select on V
+  int mode = 0;  // 1 delegate method, 2 plain radix select on V, 3 one workgroup (batched kernel)
   int alpha = 0, beta = 1;
   int dt = 0;
   uint64_t n = 0;
@@ -84,6 +84,13 @@ bool tune_lookup(int form, uint64_t n, uint32_t k, int* alpha, int* beta) {
   return false;
 }
 
+int batched_alpha(uint64_t n, uint32_t k);
+bool batched_eligible(uint64_t n, uint32_t k);
+
+// Problems up to this size (and k <= kBMaxK) finish faster in one workgroup
+// than across the device: one launch, no workspace.
+constexpr uint64_t kOneWgMaxN = 1ull << 17;
+
 int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P) {
   Plan p;
   p.n = n;
@@ -91,8 +98,13 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
   p.dt = dt;
   p.vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
   int mode = opt ? opt->mode : 0;
-  if (mode < 0 || mode > 2) return DRTOPK_EINVAL;
-  if (mode == 0) mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
+  if (mode < 0 || mode > 3) return DRTOPK_EINVAL;
+  if (mode == 3 && !batched_eligible(n, k)) return DRTOPK_EINVAL;
+  if (mode == 0) {
+    if (n <= kOneWgMaxN && batched_eligible(n, k)) mode = 3;
+    else mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
+  }
+  if (mode == 3) p.alpha = batched_alpha(n, k);
   p.mode = mode;
   p.variant = opt ? opt->variant : 0;
   if (p.variant < 0 || p.variant > 1) return DRTOPK_EINVAL;
@@ -125,7 +137,10 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
       const uint64_t c = (m / p.beta) * L + m;
       p.cap_c = c < n ? c : n;
     }
-    p.chunk = (1ull << 18) > 4 * L ? (1ull << 18) : 4 * L;
+    // one block per chunk: 4 MiB chunks (one round of blocks) stream best for
+    // beta = 1; beta > 1 needs the parallelism of 1 MiB chunks for its merges
+    const uint64_t cmin = p.beta == 1 ? (1ull << 20) : (1ull << 18);
+    p.chunk = cmin > 4 * L ? cmin : 4 * L;
   }
   if (k > (uint32_t)kSmallCap) {
     uint64_t tiles = ((uint64_t)k + kSortTile - 1) / kSortTile, t2 = 1;
@@ -545,6 +560,21 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const uint32_t* kp = static_cast<const uint32_t*>(keys);
+  if (p.mode == 3) {
+    if (filter_only) return DRTOPK_EINVAL;
+    BatchDesc d{};
+    d.keys = kp;
+    d.n = n;
+    d.k = k;
+    d.dtype = dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
+    d.alpha = (uint32_t)p.alpha;
+    d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
+    d.out_idx = kth_only ? nullptr : out_idx;
+    d.out_kth = static_cast<uint32_t*>(out_kth);
+    hipLaunchKernelGGL(k_one, dim3(1), dim3(kBT), 0, s, d);
+    if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+    return after(p, ws->ptr, s);
+  }
   if (dtype == DRTOPK_F32)
     Runner<DT_F32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
                         kth_only, filter_only, s);
@@ -563,14 +593,17 @@ int batched_alpha(uint64_t n, uint32_t k) {
   if (n <= kBSmallN) return 0;
   auto subranges = [n](int a) { return (n + (1ull << a) - 1) >> a; };
   int a = -1, b = 0;
-  if (!tune_lookup(DRTOPK_FORM_BATCHED, n, k, &a, &b) || a < 0) {
+  if (tune_lookup(DRTOPK_FORM_BATCHED, n, k, &a, &b) && a == 0) return 0;  // measured: radix select
+  if (a < 0) {
     a = rule_alpha(n, k);
     if (a < 8) a = 8;  // a wave reads 256 keys per step: shorter subranges idle lanes
   }
   if (a > 24) a = 24;
   if (a < 2) a = 2;
-  while (a < 24 && subranges(a) > kBMaxS) ++a;           // delegate vector fits the LDS
-  while (subranges(a) <= k && a > 2 && subranges(a - 1) <= kBMaxS) --a;  // more delegates than k
+  while (a < 24 && subranges(a) > kBMaxS) ++a;  // delegate vector fits the LDS
+  // at least 2k delegates where the LDS allows: with t the k-th of S subrange
+  // maxima, about -S ln(1 - k/S) <= 0.7 S elements survive, within capacity
+  while (subranges(a) < 2ull * k && a > 2 && subranges(a - 1) <= kBMaxS) --a;
   return subranges(a) > k && subranges(a) <= kBMaxS ? a : 0;
 }
 
@@ -602,7 +635,8 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
   ws->bev_pending = true;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const unsigned grid = (unsigned)(items.size() < (size_t)cus ? items.size() : (size_t)cus);
+  const size_t slots = 2 * (size_t)cus;  // two workgroups fit a CU's LDS and registers
+  const unsigned grid = (unsigned)(items.size() < slots ? items.size() : slots);
   hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, s,
                      reinterpret_cast<const BatchDesc*>(static_cast<char*>(ws->bdev) + 64), (uint32_t)items.size(),
                      static_cast<uint32_t*>(ws->bdev));
@@ -613,6 +647,15 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
 int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   if (!stats) return DRTOPK_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
+  if (p.mode == 3) {  // no control block: the workgroup keeps its state in LDS
+    std::memset(stats, 0, sizeof(*stats));
+    stats->mode = 3;
+    stats->alpha = p.alpha;
+    stats->beta = 1;
+    stats->subranges = p.alpha ? (p.n + (1ull << p.alpha) - 1) >> p.alpha : 0;
+    stats->delegates = stats->subranges;
+    return DRTOPK_OK;
+  }
   Ctl h;
   if (hipMemcpy(&h, at<Ctl>(ws, p.off_ctl), sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return DRTOPK_EDEVICE;
   std::memset(stats, 0, sizeof(*stats));

@@ -1,0 +1,120 @@
+"""Autotuner for the subrange size of the batched form (Rule 4, measured).
+
+For every bucket (floor(log2 n), floor(log2 k)) that the batched kernel owns,
+a batch of synthetic problems of that bucket (half uint32 uniform, half
+float32 normal, lengths and k uniform inside the bucket) is timed with each
+candidate alpha: Rule 4's value and its neighbours, as the kernel would
+actually run them (raised to fit its delegate vector, lowered to keep more
+delegates than k), and the workgroup radix select without delegates
+(written as alpha 0).  The fastest alpha per bucket is written to tuning.json,
+which the binding loads when it opens the library.  Every alpha gives the
+same results; only the time changes.
+
+    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _bucket_problems(torch, lg_n, lg_k, count, gen):
+    lo, hi = max(2 ** lg_n, 4097), min(2 ** (lg_n + 1) - 1, 1 << 22)
+    if lo > hi:
+        return None
+    ns = torch.randint(lo, hi + 1, (count,), generator=gen, device="cpu").tolist()
+    out = []
+    for i, n in enumerate(ns):
+        k_lo, k_hi = 2 ** lg_k, min(2 ** (lg_k + 1) - 1, n, 2048)
+        if k_lo > k_hi:
+            return None
+        k = int(torch.randint(k_lo, k_hi + 1, (1,), generator=gen, device="cpu"))
+        if i % 2 == 0:
+            t = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda").view(torch.uint32)
+        else:
+            t = torch.randn(n, device="cuda")
+        out.append((t, k))
+    return out
+
+
+def _time(torch, batch, reps):
+    batch.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        batch.run()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_batched(drt, torch, problems, reps, log=print):
+    entries = []
+    gen = torch.Generator().manual_seed(20210908)
+    torch.manual_seed(20210908)
+    drt.tune_set([])
+    for lg_n in range(12, 22):
+        for lg_k in range(0, 12):
+            probs = _bucket_problems(torch, lg_n, lg_k, problems, gen)
+            if probs is None:
+                continue
+            # the alpha the kernel runs for a problem of this bucket under a table entry a
+            rep_n, rep_k = probs[0][0].numel(), probs[0][1]
+            base = drt.batched_route(rep_n, rep_k)
+            if base[0] != 2:
+                continue
+            cands = {}
+            for a in range(max(2, base[1] - 3), min(24, base[1] + 3) + 1):
+                drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, a, 1)])
+                r, eff = drt.batched_route(rep_n, rep_k)
+                if r == 2:
+                    cands.setdefault(eff, a)
+            batch = drt.Batch(probs)
+            times = {}
+            for eff, a in sorted(cands.items()):
+                drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, a, 1)])
+                times[eff] = _time(torch, batch, reps)
+            drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, 0, 1)])  # alpha 0: radix select, no delegates
+            times[0] = _time(torch, batch, reps)
+            cands[0] = 0
+            drt.tune_set([])
+            t_rule = _time(torch, batch, reps)
+            best = min(times, key=times.get)
+            # the table holds the requested alpha; the kernel adjusts it per problem as above
+            entries.append({"form": drt.FORM_BATCHED, "lg_n": lg_n, "lg_k": lg_k, "alpha": cands[best], "beta": 1,
+                            "ms": round(times[best], 4), "rule_alpha": base[1], "rule_ms": round(t_rule, 4)})
+            log(f"n~2^{lg_n} k~2^{lg_k}: rule alpha {base[1]} {t_rule:.3f} ms, best alpha {best} "
+                f"{times[best]:.3f} ms  " + " ".join(f"{a}:{t:.3f}" for a, t in sorted(times.items())))
+            del batch, probs
+            torch.cuda.empty_cache()
+    return entries
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
+    ap.add_argument("--problems", type=int, default=512)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    import torch
+    import paper_2109_08219_amd as drt
+    if not torch.cuda.is_available():
+        sys.exit("the autotuner measures on the GPU; none is visible")
+    t0 = time.time()
+    entries = tune_batched(drt, torch, args.problems, args.reps, log=lambda s: print(s, flush=True))
+    doc = {"device": torch.cuda.get_device_name(0), "problems_per_bucket": args.problems, "reps": args.reps,
+           "seconds": round(time.time() - t0, 1), "entries": entries}
+    with open(args.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"wrote {len(entries)} entries to {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -36,7 +36,9 @@ def test_planner():
     p = drt.plan(2 ** 30, 131072)
     assert p.mode == 1 and p.beta == 2 and p.alpha == 10  # beta = 2 shifts Rule 4's alpha by 2
     # small inputs and large k/n fall back to a plain radix select
-    assert drt.plan(4096, 7).mode == 2
+    assert drt.plan(4096, 7).mode == 3  # one workgroup (n <= 2^17, k <= 2048)
+    assert drt.plan(1 << 17, 2048).mode == 3 and drt.plan((1 << 17) + 1, 2048).mode == 1
+    assert drt.plan(4096, 2049).mode == 2
     assert drt.plan(10 ** 6, 10 ** 5).mode == 2
 
 
@@ -97,10 +99,13 @@ def test_batched_routes_without_gpu():
     try:
         drt.tune_set([])
         assert drt.batched_route(1, 1) == (1, 0)
-        assert drt.batched_route(8192, 2048) == (1, 0)
-        for n in (8193, 65541, 1 << 20, 1 << 22):
+        assert drt.batched_route(4096, 2048) == (1, 0)
+        for n in (4097, 8193, 65541, 1 << 20, 1 << 22):
             for k in (1, 7, 1024, 2048):
                 r, a = drt.batched_route(n, k)
+                if -(-n // 4) <= k:  # even 4-key subranges give no more than k delegates
+                    assert (r, a) == (3, 0), (n, k, r, a)
+                    continue
                 S = -(-n // (1 << a))
                 assert r == 2 and 2 <= a <= 24 and k < S <= 4096, (n, k, r, a)
         assert drt.batched_route(1 << 20, 1) == (2, 11)  # Rule 4: floor((20 - 0 + 3) / 2)

@@ -68,7 +68,7 @@ def workload_hosts(count, seed):
 
 
 def test_routes_are_planned():
-    assert drt.batched_route(8192, 100) == (1, 0)
+    assert drt.batched_route(4096, 100) == (1, 0)
     r, a = drt.batched_route(1 << 20, 1024)
     assert r == 2 and a >= 8 and -(-(1 << 20) // (1 << a)) <= 4096
     assert drt.batched_route((1 << 22) + 1, 10)[0] == 0
@@ -87,16 +87,23 @@ def test_workload_sample_exact():
 def test_each_route():
     hosts = []
     # sorted outright in the workgroup
-    for n, k in [(1, 1), (2, 2), (3, 1), (100, 37), (1000, 1000), (4096, 2048), (4097, 5), (8192, 2048)]:
+    for n, k in [(1, 1), (2, 2), (3, 1), (100, 37), (1000, 1000), (4095, 3), (4096, 2048)]:
         for kind in ("uniform_u32", "normal_f32", "heavydup_u32"):
             x, dt = synth.keys(kind, n, 31 + n)
+            assert drt.batched_route(n, k)[0] == 1
             hosts.append((x, dt, k))
-    # delegate method in LDS, ragged last subrange
-    for n, k in [(8193, 1), (8193, 2048), (65541, 1), (65541, 7), (65541, 2048), ((1 << 20) + 5, 1000),
-                 ((1 << 22), 2048), ((1 << 22) - 3, 1)]:
+    # delegate method in LDS, short and long subranges, ragged last subrange
+    for n, k in [(4097, 5), (8193, 1), (8193, 2048), (65541, 1), (65541, 7), (65541, 2048), ((1 << 20) + 5, 1000),
+                 ((1 << 22), 2048), ((1 << 22) - 3, 1), (300000, 1), (300000, 1999)]:
         for kind in ("uniform_u32", "normal_f32"):
             x, dt = synth.keys(kind, n, 57 + n)
             assert drt.batched_route(n, k)[0] == 2
+            hosts.append((x, dt, k))
+    # too few subranges for k: radix select in the workgroup
+    for n, k in [(8192, 2048), (6000, 1600)]:
+        for kind in ("uniform_u32", "heavydup_u32"):
+            x, dt = synth.keys(kind, n, 71 + n)
+            assert drt.batched_route(n, k)[0] == 3
             hosts.append((x, dt, k))
     # survivors overflow the workgroup: ascending input and 16 distinct values
     for n, k in [(1 << 18, 2000), (100003, 64), (1 << 20, 2048)]:
