@@ -41,7 +41,8 @@ HBM_PEAK_GBS = 8000.0
 N = 1 << 30
 KS = (1, 1024, 131072)
 CPU_SAMPLE = 1 << 26
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delegate_pass_traffic.json")
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delegate_pass_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08219_amd", "csrc", f) for f in ("kernels.h", "internal.h")]
 
 
@@ -55,15 +56,20 @@ def kernel_hash() -> str:
 
 def traffic_for_current_kernel():
     """HBM bytes per delegate-pass launch from the committed rocprofv3 counter
-    runs, if they were taken on the current kernel source; otherwise None."""
+    runs (``key = value`` lines), if they were taken on the current kernel
+    source; otherwise None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            kv = dict(line.split("=", 1) for line in f if "=" in line and not line.startswith("#"))
+    except OSError:
         return None
-    if t.get("kernel_source_sha256_16") != kernel_hash():
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _gpu_keys(torch, kind, n, gen):
@@ -147,6 +153,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy, whose HBM counters calibrate the traffic figure")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -171,6 +179,17 @@ def main() -> int:
     t_f = torch.from_numpy(x_f).to(dev)
     sample_f = x_f[:CPU_SAMPLE].copy()
     del x_f
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale factor of the traffic measurement (1 GiB each way)
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cases = []
     for name, t in (("u32", t_u), ("f32", t_f)):
         for k in KS:

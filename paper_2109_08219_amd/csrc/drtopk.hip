@@ -319,11 +319,12 @@ struct PhaseMarks {
 template <int DT>
 struct Runner {
   static void delegate(const Plan& p, const uint32_t* keys, uint32_t* dkey, uint32_t* didx, Ctl* ctl,
-                       hipStream_t st) {
+                       hipStream_t st, DirectOut out = DirectOut{nullptr, nullptr, nullptr, 0}) {
     if (p.alpha >= 2) {
       const unsigned g = (unsigned)((p.n + p.chunk - 1) / p.chunk);
 #define DRTOPK_DEL(B, V) \
-  hipLaunchKernelGGL((k_delegate<DT, B, V>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.chunk, dkey, didx, ctl, p.kD)
+  hipLaunchKernelGGL((k_delegate<DT, B, V>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.chunk, dkey, didx, ctl, p.kD, \
+                     out)
       switch (p.beta * 2 + (p.vec ? 1 : 0)) {
         case 2: DRTOPK_DEL(1, false); break;
         case 3: DRTOPK_DEL(1, true); break;
@@ -338,7 +339,8 @@ struct Runner {
     } else {
       const unsigned g = grid_for(p.S, 256, 4096);
 #define DRTOPK_DELT(B) \
-  hipLaunchKernelGGL((k_delegate_thread<DT, B>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.S, dkey, didx, ctl, p.kD)
+  hipLaunchKernelGGL((k_delegate_thread<DT, B>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.S, dkey, didx, ctl, \
+                     p.kD, out)
       switch (p.beta) {
         case 1: DRTOPK_DELT(1); break;
         case 2: DRTOPK_DELT(2); break;
@@ -426,6 +428,11 @@ struct Runner {
     if (p.mode == 1 && p.variant == 0) {
       uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
       uint32_t* didx = at<uint32_t>(ws, p.off_didx);
+      if (k == 1 && !filter_only) {  // the largest delegate is the answer (Rule 1)
+        delegate(p, keys, dkey, didx, ctl, st, DirectOut{out_vals, out_idx, out_kth, 1});
+        pm.mid(st);
+        return;
+      }
       delegate(p, keys, dkey, didx, ctl, st);
       pm.mid(st);
       TailArgs ta;

@@ -79,6 +79,7 @@ struct Ctl {
   uint32_t uniq_idx;  // position of a unique entry found by a tail pass
   uint32_t tpub[2];   // threshold t published by block 0 of the tail (coherent stores)
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
+  uint64_t max1;  // largest delegate composite (k = 1 is answered by the delegate pass)
   uint32_t nq;    // subranges to re-read
   uint32_t nc;    // survivors
   uint32_t nout;  // compacted outputs (large-survivor path)

@@ -211,7 +211,7 @@ __device__ __forceinline__ void stage_flush(Stage<CAP>& S, uint32_t* gcount, uin
 
 template <int BETA>
 __device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb, uint32_t* dkey,
-                                               uint32_t* didx, uint32_t* lh) {
+                                               uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
 #pragma unroll
   for (int j = 0; j < BETA; ++j) {
     const uint32_t kk = comp_key(tb.c[j]);
@@ -220,18 +220,38 @@ __device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb,
     atomicAdd(&lh[top_bin(kk)], 1u);
     atomicAdd(&lh[kBins + log_bin(kk)], 1u);
   }
+  atomicMax((unsigned long long*)bmax, (unsigned long long)tb.c[0]);
 }
+
+template <int DT>
+__device__ __forceinline__ void write_out(uint64_t c, uint32_t r, uint32_t k, uint32_t* out_vals,
+                                          uint32_t* out_idx, uint32_t* out_kth) {
+  const uint32_t v = dec<DT>(comp_key(c));
+  if (out_vals) out_vals[r] = v;
+  if (out_idx) out_idx[r] = comp_pos(c);
+  if (out_kth && r == k - 1) *out_kth = v;
+}
+
+// Outputs written by the delegate pass itself when k = 1: the largest
+// element is the largest delegate (Rule 1), so no later step is needed.
+struct DirectOut {
+  uint32_t* vals;
+  uint32_t* idx;
+  uint32_t* kth;
+  int on;
+};
 
 // End of the delegate pass: the last block finds, under both monotone maps,
 // the bin holding the kD-th largest delegate, and keeps the map whose cut
 // leaves the smaller set W (all delegates in that bin or above).
 __device__ inline void finish_delegates(const uint32_t* lh, Ctl* ctl, uint32_t kD, uint32_t* s_scan,
-                                        uint32_t* s_out, int* s_last) {
+                                        uint32_t* s_out, int* s_last, const uint64_t* bmax, bool direct) {
   for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
     const uint32_t a = lh[i], b = lh[kBins + i];
     if (a) atomicAdd(&ctl->histD[0][i], a);
     if (b) atomicAdd(&ctl->histL[i], b);
   }
+  if (direct && threadIdx.x == 0 && *bmax) atomicMax((unsigned long long*)&ctl->max1, (unsigned long long)*bmax);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) *s_last = (atomicAdd(&ctl->ticketD[0], 1u) == gridDim.x - 1) ? 1 : 0;
@@ -282,7 +302,7 @@ constexpr int kUnroll = 8;  // 128-bit loads in flight per lane
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                               uint64_t wlo, uint64_t whi, bool fast,
-                                              uint32_t* dkey, uint32_t* didx, uint32_t* lh) {
+                                              uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint64_t wps_mask = (1ull << (alpha - 8)) - 1;  // wave-loads per subrange - 1
   const uint64_t nwl = (whi + 255 - wlo) >> 8;
@@ -312,7 +332,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
         if (((j + 1) & wps_mask) == 0 || j + 1 == nwl) {
 #pragma unroll
           for (int m = 1; m < 64; m <<= 1) tb.merge_xor(m);
-          if (lane == 0) emit_delegates<BETA>((wlo + (j << 8)) >> alpha, tb, dkey, didx, lh);
+          if (lane == 0) emit_delegates<BETA>((wlo + (j << 8)) >> alpha, tb, dkey, didx, lh, bmax);
           tb.clear();
         }
       }
@@ -325,7 +345,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                uint64_t wlo, uint64_t whi, bool fast,
-                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh) {
+                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint32_t gl = 1u << (alpha - 2);  // lanes per subrange
   const uint64_t nwl = (whi + 255 - wlo) >> 8;
@@ -353,7 +373,7 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
         for (int c = 0; c < 4; ++c)
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
         for (uint32_t m = 1; m < gl; m <<= 1) tb.merge_xor((int)m);
-        if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh);
+        if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh, bmax);
       }
     }
   }
@@ -364,12 +384,14 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
 template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                   uint64_t chunk, uint32_t* __restrict__ dkey,
-                                                  uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
+                                                  uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k, DirectOut out) {
   __shared__ uint32_t lh[2 * kBins];
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
+  __shared__ uint64_t s_bmax;
   for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
+  if (threadIdx.x == 0) s_bmax = 0;
   __syncthreads();
   const uint32_t wave = threadIdx.x >> 6;
   const uint64_t wlen = chunk >> 2;
@@ -377,11 +399,12 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
-    if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh);
-    else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh);
+    if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax, out.on != 0);
+  if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 
 // Subranges of 1 or 2 elements, or any alpha when the planner asks for the
@@ -389,12 +412,15 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
 template <int DT, int BETA>
 __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restrict__ keys, uint64_t n,
                                                          int alpha, uint64_t S, uint32_t* __restrict__ dkey,
-                                                         uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k) {
+                                                         uint32_t* __restrict__ didx, Ctl* ctl, uint32_t k,
+                                                         DirectOut out) {
   __shared__ uint32_t lh[2 * kBins];
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
+  __shared__ uint64_t s_bmax;
   for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
+  if (threadIdx.x == 0) s_bmax = 0;
   __syncthreads();
   for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < S; s += (uint64_t)gridDim.x * 256) {
     TopB<BETA> tb;
@@ -402,10 +428,11 @@ __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restr
     const uint64_t lo = s << alpha;
     const uint64_t hi = (lo + (1ull << alpha)) < n ? lo + (1ull << alpha) : n;
     for (uint64_t p = lo; p < hi; ++p) tb.push(comp(enc<DT>(keys[p]), (uint32_t)p));
-    emit_delegates<BETA>(s, tb, dkey, didx, lh);
+    emit_delegates<BETA>(s, tb, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax, out.on != 0);
+  if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,14 +586,6 @@ __device__ __forceinline__ uint64_t src_comp(const uint32_t* key, const uint32_t
   return comp(src_key<SRC, DT>(key, i), src_pos<SRC>(idx, i));
 }
 
-template <int DT>
-__device__ __forceinline__ void write_out(uint64_t c, uint32_t r, uint32_t k, uint32_t* out_vals,
-                                          uint32_t* out_idx, uint32_t* out_kth) {
-  const uint32_t v = dec<DT>(comp_key(c));
-  if (out_vals) out_vals[r] = v;
-  if (out_idx) out_idx[r] = comp_pos(c);
-  if (out_kth && r == k - 1) *out_kth = v;
-}
 
 // One workgroup: all `count` (<= kSmallCap) entries sorted in LDS, first k written.
 template <int SRC, int DT>

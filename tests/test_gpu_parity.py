@@ -187,7 +187,7 @@ def test_side_stream_and_repeat():
 
 def test_kth_select_matches():
     for kind in KINDS:
-        for n, k in [(100, 37), (70000, 1), (70000, 9999), ((1 << 20) + 1, 20000)]:
+        for n, k in [(100, 37), (70000, 1), (70000, 9999), (300001, 1), ((1 << 20) + 1, 1), ((1 << 20) + 1, 20000)]:
             x, dt = synth.keys(kind, n, 41)
             say("kth", kind, n, k)
             got = to_np(drt.kth_select(dev(x), k))[0]
