@@ -127,7 +127,7 @@ int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha)
  *   mode   0 = planner's choice, 1 = delegate method, 2 = plain radix select
  *          over V with no delegates, 3 = the whole problem in one workgroup
  *          (the batched form's kernel, one launch; n <= 2^22, k <= 2048; the
- *          planner takes it for n <= 2^17; alpha is then the batched form's)
+ *          planner takes it for n <= 2^16; alpha is then the batched form's)
  *   variant  implementation of the steps after the delegate pass: 0 = one
  *          cooperative kernel (default), 1 = one kernel per step.  Both give
  *          bit-identical results. */
@@ -207,11 +207,14 @@ int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes);
 /* Serving loop: continuous batching of requests over device-resident arrays
  * (each request is a drtopk_problem_t: device pointers, the caller keeps them
  * alive until the request completes).  A server owns `streams` launch streams
- * and one dispatcher thread.  Whenever a stream is free, the dispatcher admits
- * queued requests in arrival order while the summed footprint of admitted,
- * unfinished requests stays within hbm_budget (a request larger than the
- * budget is admitted alone), at most max_batch per launch, and launches them
- * together with topk_select_batched on that stream.  Requests arriving while
+ * and one dispatcher thread.  Whenever a stream is free, the dispatcher looks
+ * at the oldest queued request: one that a workgroup cannot own (n > 2^22 or
+ * k > 2048) is launched alone through the single-problem path; otherwise the
+ * queued small requests are admitted in arrival order while the summed
+ * footprint of admitted, unfinished requests stays within hbm_budget (a
+ * request larger than the budget is admitted alone), at most max_batch per
+ * launch, and launched together with topk_select_batched on that stream (a
+ * launch of one request calls topk_select directly).  Requests arriving while
  * launches run join the next launch, so their work overlaps on the device.
  * Results are bit-identical to topk_select / kth_select on each request
  * alone.  plain = 1 turns the server into the per-request baseline: one

@@ -4,12 +4,13 @@
 // largest first (the host orders them), and runs the delegate method for one
 // problem entirely in its LDS:
 //   delegate vector (Rule 1, beta = 1): one wave per subrange of 2^alpha keys;
-//   t = the k-th largest delegate: the delegate vector sorted in registers;
+//   t = the k-th largest delegate: an LDS radix select over the delegates;
 //   survivors (Rule 2): t itself plus every element ranked >= t in the k-1
 //     subranges whose delegate ranks above t (an element >= t lies either in
 //     such a subrange or is t), read as one virtual concatenated vector;
 //   output: survivors sorted in registers, the first k written.
-// Problems of at most kBSmallN keys are sorted outright.  A problem whose
+// Problems of at most kBSmallN keys are selected in LDS directly (the k-th
+// by radix select, then the k at or above it sorted).  A problem whose
 // survivors overflow the LDS (adversarial inputs), or whose delegate vector
 // would not exceed k, takes a block-level MSD radix select over its keys.
 // Two workgroups share a CU, so one streams keys while the other sorts.
@@ -23,13 +24,14 @@ namespace drtopk {
 
 constexpr int kBT = 512;                  // threads per workgroup (two workgroups per CU)
 constexpr int kBWaves = kBT / 64;
-constexpr uint32_t kBSmallN = 4096;       // problems this small are sorted outright
+constexpr uint32_t kBSmallN = 4096;       // problems this small are selected in LDS directly
 constexpr uint32_t kBMaxS = 4096;         // delegate vector capacity (LDS)
 constexpr uint32_t kBSurv = 4096;         // survivor capacity (LDS)
 constexpr uint32_t kBMaxK = 2048;         // largest k handled in a workgroup
 constexpr uint64_t kBMaxN = 1ull << 22;   // largest n handled in a workgroup
 constexpr int kBU = 8;                    // 1 KiB wave loads in flight per wave step
 constexpr uint32_t kBStep = 256 * kBU;    // keys per wave step
+constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 for gfx9-family raw buffers
 
 // One problem as the kernel sees it (64 bytes).
 struct BatchDesc {
@@ -47,11 +49,14 @@ struct BatchDesc {
 static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
 
 struct BatchSmem {
-  uint64_t D[kBMaxS];     // delegate composites, then sorted
+  uint64_t D[kBMaxS];     // delegate composites; also the exchange buffer of small sorts
   uint64_t surv[kBSurv];  // survivors, also the exchange buffer of their sort
-  uint32_t hist[kBins];
-  uint32_t scan[kBT];
+  uint32_t hist[kBins];   // digit histograms; then the list of qualifying subranges
+  uint32_t wsum[kBWaves];
+  uint64_t sel;
+  uint64_t tail_del;      // delegate of the subrange holding the last n mod 4 keys
   uint32_t nsurv;
+  uint32_t nq;
   uint32_t item;
   uint32_t out[4];
 };
@@ -65,28 +70,58 @@ __device__ __forceinline__ uint64_t wave_max64(uint64_t m) {
   return m;
 }
 
+// The keys of one problem behind a raw buffer resource: loads are plain
+// buffer loads (base address in scalar registers, 32-bit offsets), and whole
+// dwords at or beyond `nrec` keys read 0.  VEC: 16-byte loads of 4 keys at a
+// multiple of 4 (the base is 16-byte aligned and nrec a multiple of 4, so a
+// load is either wholly inside or wholly outside); otherwise 4-byte loads.
+template <bool VEC>
+struct Keys {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Keys(const uint32_t* p, uint32_t nrec)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(p), (short)0, (int)(nrec * 4u), kBufWord3)) {}
+  __device__ __forceinline__ void load4(uint32_t p, uint32_t (&v)[4]) const {
+    if constexpr (VEC) {
+      const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(p * 4u), 0, 0);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)((p + c) * 4u), 0, 0);
+    }
+  }
+};
+
+// Keys [0, n4) go through the streaming loops; with 16-byte loads n4 = n
+// rounded down to a multiple of 4 and the last n - n4 keys are read one by one.
+template <bool VEC>
+__device__ __forceinline__ uint32_t vec_end(uint32_t n) {
+  return VEC ? (n & ~3u) : n;
+}
+
 // Bin holding the rank-th largest entry of an LDS histogram (each thread owns
-// kBins / kBT consecutive bins, highest first): sm.out = {bin, rank within the
-// bin, found, count of the bin}.
+// kBins / kBT consecutive bins, highest first; wave prefix sums, one barrier):
+// sm.out = {bin, rank within the bin, found, count of the bin}.
 __device__ inline void bb_bucket(const uint32_t* h, uint32_t rank, BatchSmem& sm) {
   constexpr int PER = kBins / kBT;
   const int t = threadIdx.x;
+  const uint32_t lane = lane_id(), wave = t >> 6;
   uint32_t c[PER], sum = 0;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     c[j] = h[kBins - 1 - PER * t - j];
     sum += c[j];
   }
-  sm.scan[t] = sum;
+  uint32_t x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, o);
+    if ((int)lane >= o) x += y;
+  }
+  if (lane == 63) sm.wsum[wave] = x;
   if (t == 0) { sm.out[0] = 0; sm.out[1] = 0; sm.out[2] = 0; sm.out[3] = 0; }
   __syncthreads();
-  for (int off = 1; off < kBT; off <<= 1) {
-    const uint32_t x = t >= off ? sm.scan[t - off] : 0u;
-    __syncthreads();
-    sm.scan[t] += x;
-    __syncthreads();
-  }
-  uint32_t excl = sm.scan[t] - sum;
+  uint32_t excl = x - sum;
+  for (uint32_t w = 0; w < wave; ++w) excl += sm.wsum[w];
   if (excl < rank && rank <= excl + sum) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
@@ -100,29 +135,6 @@ __device__ inline void bb_bucket(const uint32_t* h, uint32_t rank, BatchSmem& sm
     }
   }
   __syncthreads();
-}
-
-// Sorts `cnt` composites of LDS array `src` (descending) and leaves them
-// there; `src` holds at least E * kBT entries.
-template <int E>
-__device__ __noinline__ void b_sort_lds_e(uint64_t* src, uint32_t cnt) {
-  uint64_t v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const uint32_t g = threadIdx.x * E + e;
-    v[e] = g < cnt ? src[g] : 0ull;
-  }
-  block_bitonic<E, kBT>(v, src);
-#pragma unroll
-  for (int e = 0; e < E; ++e) src[threadIdx.x * E + e] = v[e];
-  __syncthreads();
-}
-
-__device__ inline void b_sort_lds(uint64_t* src, uint32_t cnt) {
-  if (cnt <= 1u * kBT) b_sort_lds_e<1>(src, cnt);
-  else if (cnt <= 2u * kBT) b_sort_lds_e<2>(src, cnt);
-  else if (cnt <= 4u * kBT) b_sort_lds_e<4>(src, cnt);
-  else b_sort_lds_e<8>(src, cnt);
 }
 
 // Sorts `cnt` composites from LDS array `src` and writes the first `k` as
@@ -145,7 +157,7 @@ __device__ __noinline__ void b_sort_write_e(uint64_t* src, uint32_t cnt, uint32_
   }
 }
 
-// cnt <= kBSurv, k <= cnt.
+// cnt <= kBT * 8, k <= cnt.
 template <int DT>
 __device__ inline void b_sort_write(uint64_t* src, uint32_t cnt, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
                                     uint32_t* out_kth) {
@@ -155,32 +167,69 @@ __device__ inline void b_sort_write(uint64_t* src, uint32_t cnt, uint32_t k, uin
   else b_sort_write_e<DT, 8>(src, cnt, k, out_vals, out_idx, out_kth);
 }
 
-// Loads 4 consecutive keys at p (p a multiple of 4); those at or beyond
-// `end` read as 0 and are ignored by the caller.
-__device__ __forceinline__ void b_load4(const uint32_t* keys, uint32_t p, uint32_t end, bool vec, uint32_t (&v)[4]) {
-  if (vec && p + 4 <= end) {
-    const u32x4 x = *reinterpret_cast<const u32x4*>(keys + p);
-    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-  } else {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = p + c < end ? keys[p + c] : 0u;
+// The rank-th largest (1-based) of the distinct composites a[0..cnt) in LDS:
+// MSD radix select, one 11/11/10-bit digit per pass, stopping once the class
+// holding rank r has a single member.  Identical in every thread.
+__device__ inline uint64_t lds_select(const uint64_t* a, uint32_t cnt, uint32_t rank, BatchSmem& sm) {
+  uint64_t prefix = 0, mask = 0;
+  uint32_t r = rank;
+  for (int p = 0; p < kPasses; ++p) {
+    for (int i = threadIdx.x; i < kBins; i += kBT) sm.hist[i] = 0;
+    __syncthreads();
+    const int sh = pass_shift(p);
+    const uint32_t dm = (1u << pass_bits(p)) - 1;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBT) {
+      const uint64_t x = a[i];
+      if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
+    }
+    __syncthreads();
+    bb_bucket(sm.hist, r, sm);
+    prefix |= (uint64_t)sm.out[0] << sh;
+    mask |= (uint64_t)dm << sh;
+    r = sm.out[1];
+    if (sm.out[3] == 1u) break;  // always so after the last digit
   }
-}
-
-// Problems of at most kBSmallN keys: load all composites, sort, write.
-template <int DT>
-__device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
-  const uint32_t n = (uint32_t)d.n;
-  const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  for (uint32_t i = threadIdx.x * 4; i < n; i += kBT * 4) {
-    uint32_t v[4];
-    b_load4(d.keys, i, n, vec, v);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (i + c < n) sm.surv[i + c] = comp(enc<DT>(v[c]), i + c);
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBT) {
+    const uint64_t x = a[i];
+    if ((x & mask) == prefix) sm.sel = x;  // the class's single member
   }
   __syncthreads();
-  b_sort_write<DT>(sm.surv, n, d.k, d.out_vals, d.out_idx, d.out_kth);
+  const uint64_t t = sm.sel;
+  __syncthreads();
+  return t;
+}
+
+// Problems of at most kBSmallN keys: composites into LDS, the k-th by radix
+// select, the k at or above it compacted and sorted.
+template <int DT, bool VEC>
+__device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
+  const uint32_t n = (uint32_t)d.n, k = d.k, n4 = vec_end<VEC>(n);
+  const Keys<VEC> ks(d.keys, n4);
+  for (uint32_t i = threadIdx.x * 4; i < n4; i += kBT * 4) {
+    uint32_t v[4];
+    ks.load4(i, v);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (i + c < n4) sm.surv[i + c] = comp(enc<DT>(v[c]), i + c);
+  }
+  if (threadIdx.x == 0)
+    for (uint32_t i = n4; i < n; ++i) sm.surv[i] = comp(enc<DT>(d.keys[i]), i);
+  __syncthreads();
+  uint32_t cnt = n;
+  uint64_t* src = sm.surv;
+  if (k < n) {
+    const uint64_t T = lds_select(sm.surv, n, k, sm);
+    if (threadIdx.x == 0) sm.nsurv = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kBT) {
+      const uint64_t x = sm.surv[i];
+      if (x >= T) sm.D[atomicAdd(&sm.nsurv, 1u)] = x;  // exactly k
+    }
+    __syncthreads();
+    cnt = k;
+    src = sm.D;
+  }
+  b_sort_write<DT>(src, cnt, k, d.out_vals, d.out_idx, d.out_kth);
 }
 
 // Block-level MSD radix select over the problem's 64-bit composites: each
@@ -189,10 +238,10 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
 // soon as the elements ranked above the class plus the class itself fit the
 // LDS, they are compacted, sorted and the first k written: two passes over
 // the keys for typical inputs, at most seven for massive ties.
-template <int DT>
+template <int DT, bool VEC>
 __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
-  const uint32_t n = (uint32_t)d.n, k = d.k;
-  const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
+  const uint32_t n = (uint32_t)d.n, k = d.k, n4 = vec_end<VEC>(n);
+  const Keys<VEC> ks(d.keys, n4);
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   uint64_t prefix = 0, mask = 0;
   uint32_t r = k, above = 0;
@@ -201,19 +250,24 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
     __syncthreads();
     const int sh = pass_shift(p);
     const uint32_t dm = (1u << pass_bits(p)) - 1;
-    for (uint32_t base = wave * kBStep; base < n; base += kBWaves * kBStep) {
+    for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
       uint32_t v[kBU][4];
 #pragma unroll
-      for (int j = 0; j < kBU; ++j) b_load4(d.keys, base + j * 256 + lane * 4, n, vec, v[j]);
+      for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
 #pragma unroll
       for (int j = 0; j < kBU; ++j)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t i = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(enc<DT>(v[j][c]), i);
-          if (i < n && (x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
+          if (i < n4 && (x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
         }
     }
+    if (threadIdx.x == 0)
+      for (uint32_t i = n4; i < n; ++i) {
+        const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+        if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
+      }
     __syncthreads();
     bb_bucket(sm.hist, r, sm);
     prefix |= (uint64_t)sm.out[0] << sh;
@@ -225,39 +279,47 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
   // every element ranked above the class, and the class: (x & mask) >= prefix
   if (threadIdx.x == 0) sm.nsurv = 0;
   __syncthreads();
-  for (uint32_t base = wave * kBStep; base < n; base += kBWaves * kBStep) {
+  for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
     uint32_t v[kBU][4];
 #pragma unroll
-    for (int j = 0; j < kBU; ++j) b_load4(d.keys, base + j * 256 + lane * 4, n, vec, v[j]);
+    for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
 #pragma unroll
     for (int j = 0; j < kBU; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t i = base + j * 256 + lane * 4 + c;
         const uint64_t x = comp(enc<DT>(v[j][c]), i);
-        if (i < n && (x & mask) >= prefix) {
+        if (i < n4 && (x & mask) >= prefix) {
           const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
           if (slot < kBSurv) sm.surv[slot] = x;
         }
       }
   }
+  if (threadIdx.x == 0)
+    for (uint32_t i = n4; i < n; ++i) {
+      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      if ((x & mask) >= prefix) {
+        const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
+        if (slot < kBSurv) sm.surv[slot] = x;
+      }
+    }
   __syncthreads();
   const uint32_t ns = sm.nsurv < kBSurv ? sm.nsurv : kBSurv;
   b_sort_write<DT>(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth);
 }
 
-// Delegate vector for subranges of at least 256 keys: waves stream the problem
-// in steps of kBStep keys with kBU 1 KiB loads in flight; each 256-key block
-// lies inside one subrange, whose delegate takes the block's maximum by an LDS
+// Delegate vector for subranges of at least 256 keys: waves stream the keys
+// in steps of kBStep with kBU 1 KiB loads in flight; each 256-key block lies
+// inside one subrange, whose delegate takes the block's maximum by an LDS
 // atomic max (D starts at 0, below every composite of a real element).
-template <int DT>
-__device__ inline void b_delegates_wide(const BatchDesc& d, BatchSmem& sm, bool vec) {
-  const uint32_t n = (uint32_t)d.n, alpha = d.alpha, L = 1u << alpha;
+template <int DT, bool VEC>
+__device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, BatchSmem& sm) {
+  const uint32_t L = 1u << alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t base = wave * kBStep; base < n; base += kBWaves * kBStep) {
+  for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
     uint32_t v[kBU][4];
 #pragma unroll
-    for (int j = 0; j < kBU; ++j) b_load4(d.keys, base + j * 256 + lane * 4, n, vec, v[j]);
+    for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
     if (L >= kBStep) {
       uint64_t m = 0;
 #pragma unroll
@@ -266,7 +328,7 @@ __device__ inline void b_delegates_wide(const BatchDesc& d, BatchSmem& sm, bool 
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(enc<DT>(v[j][c]), p);
-          if (p < n && x > m) m = x;
+          if (p < n4 && x > m) m = x;
         }
       m = wave_max64(m);
       if (lane == 0) atomicMax((unsigned long long*)&sm.D[base >> alpha], (unsigned long long)m);
@@ -278,10 +340,10 @@ __device__ inline void b_delegates_wide(const BatchDesc& d, BatchSmem& sm, bool 
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(enc<DT>(v[j][c]), p);
-          if (p < n && x > m) m = x;
+          if (p < n4 && x > m) m = x;
         }
         m = wave_max64(m);
-        if (lane == 0 && base + j * 256 < n)
+        if (lane == 0 && base + j * 256 < n4)
           atomicMax((unsigned long long*)&sm.D[(base + j * 256) >> alpha], (unsigned long long)m);
       }
     }
@@ -291,15 +353,14 @@ __device__ inline void b_delegates_wide(const BatchDesc& d, BatchSmem& sm, bool 
 // Delegate vector for subranges of 4..128 keys: each 256-key wave-load holds
 // whole subranges, 2^(alpha-2) lanes each; a segmented butterfly gives each
 // subrange's maximum to its first lane.
-template <int DT>
-__device__ inline void b_delegates_narrow(const BatchDesc& d, BatchSmem& sm, bool vec) {
-  const uint32_t n = (uint32_t)d.n, alpha = d.alpha;
+template <int DT, bool VEC>
+__device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, BatchSmem& sm) {
   const uint32_t G = 1u << (alpha - 2);  // lanes per subrange
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t base = wave * kBStep; base < n; base += kBWaves * kBStep) {
+  for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
     uint32_t v[kBU][4];
 #pragma unroll
-    for (int j = 0; j < kBU; ++j) b_load4(d.keys, base + j * 256 + lane * 4, n, vec, v[j]);
+    for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
 #pragma unroll
     for (int j = 0; j < kBU; ++j) {
       const uint32_t p = base + j * 256 + lane * 4;
@@ -307,23 +368,24 @@ __device__ inline void b_delegates_narrow(const BatchDesc& d, BatchSmem& sm, boo
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint64_t x = comp(enc<DT>(v[j][c]), p + c);
-        if (p + c < n && x > m) m = x;
+        if (p + c < n4 && x > m) m = x;
       }
       for (uint32_t o = 1; o < G; o <<= 1) {
         const uint64_t y = shfl_xor64(m, (int)o);
         m = y > m ? y : m;
       }
-      if ((lane & (G - 1)) == 0 && p < n) sm.D[p >> alpha] = m;
+      if ((lane & (G - 1)) == 0 && p < n4) atomicMax((unsigned long long*)&sm.D[p >> alpha], (unsigned long long)m);
     }
   }
 }
 
-// Survivors: every element ranked >= t in the subranges of the k-1 delegates
-// above t (sm.D[0..k-2], sorted), read as one virtual vector of
-// (k-1) * 2^alpha keys in 16-byte pieces (a piece never crosses a subrange).
-template <int DT>
-__device__ inline void b_survivors(const BatchDesc& d, BatchSmem& sm, bool vec, uint64_t t) {
-  const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, L = 1u << alpha;
+// Survivors: every element ranked >= t in the k-1 subranges listed in Q,
+// read as one virtual vector of (k-1) * 2^alpha keys in 4-key pieces (a
+// piece never crosses a subrange).
+template <int DT, bool VEC>
+__device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k, uint32_t alpha, const uint32_t* Q,
+                                   uint64_t t, BatchSmem& sm) {
+  const uint32_t L = 1u << alpha;
   const uint32_t total = (k - 1) << alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   for (uint32_t base = wave * kBStep; base < total; base += kBWaves * kBStep) {
@@ -331,50 +393,65 @@ __device__ inline void b_survivors(const BatchDesc& d, BatchSmem& sm, bool vec, 
 #pragma unroll
     for (int j = 0; j < kBU; ++j) {
       const uint32_t e = base + j * 256 + lane * 4;
-      pb[j] = 0xFFFFFFFFu;
-      if (e < total) {
-        const uint32_t s = comp_pos(sm.D[e >> alpha]) >> alpha;
-        pb[j] = (s << alpha) + (e & (L - 1));
-        b_load4(d.keys, pb[j], n, vec, v[j]);
-      }
+      // past the virtual vector: a position at n4 or beyond reads zeros and is ignored
+      pb[j] = e < total ? (Q[e >> alpha] << alpha) + (e & (L - 1)) : n4;
+      ks.load4(pb[j], v[j]);
     }
 #pragma unroll
-    for (int j = 0; j < kBU; ++j) {
-      if (pb[j] == 0xFFFFFFFFu) continue;
+    for (int j = 0; j < kBU; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t p = pb[j] + c;
         const uint64_t x = comp(enc<DT>(v[j][c]), p);
-        if (p < n && x >= t) {
+        if (p < n4 && x >= t) {
           const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
           if (slot < kBSurv) sm.surv[slot] = x;
         }
       }
-    }
   }
 }
 
 // The delegate method for one problem; false if the survivors overflow LDS
 // (nothing has been written then).
-template <int DT>
+template <int DT, bool VEC>
 __device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
-  const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha;
+  const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
-  const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (alpha >= 8) {
-    for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
-    __syncthreads();
-    b_delegates_wide<DT>(d, sm, vec);
-  } else {
-    b_delegates_narrow<DT>(d, sm, vec);
+  const Keys<VEC> ks(d.keys, n4);
+  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
+  __syncthreads();
+  if (alpha >= 8) b_delegates_wide<DT, VEC>(ks, n4, alpha, sm);
+  else b_delegates_narrow<DT, VEC>(ks, n4, alpha, sm);
+  if (threadIdx.x == 0 && n4 < n) {  // the last n mod 4 keys, all in one subrange
+    uint64_t m = 0;
+    for (uint32_t i = n4; i < n; ++i) {
+      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      m = x > m ? x : m;
+    }
+    atomicMax((unsigned long long*)&sm.D[n4 >> alpha], (unsigned long long)m);
   }
   __syncthreads();
-  b_sort_lds(sm.D, S);  // descending: D[k-1] is t, D[0..k-2] the delegates above it
-  if (threadIdx.x == 0) sm.nsurv = 1;
-  const uint64_t t = sm.D[k - 1];
-  if (threadIdx.x == 0) sm.surv[0] = t;  // t itself: its subrange is not re-read
+  if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[n4 >> alpha] : 0;
+  const uint64_t t = lds_select(sm.D, S, k, sm);  // Rule 2: the k-th delegate
+  // the k-1 subranges whose delegate ranks above t (order irrelevant)
+  uint32_t* Q = sm.hist;
+  if (threadIdx.x == 0) { sm.nq = 0; sm.nsurv = 1; sm.surv[0] = t; }  // t itself: its subrange is not re-read
   __syncthreads();
-  b_survivors<DT>(d, sm, vec, t);
+  for (uint32_t i = threadIdx.x; i < S; i += kBT) {
+    const uint64_t x = sm.D[i];
+    if (x > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(x) >> alpha;
+  }
+  __syncthreads();
+  b_survivors<DT, VEC>(ks, n4, k, alpha, Q, t, sm);
+  if (threadIdx.x == 0 && n4 < n && sm.tail_del > t) {  // the last keys, when their subrange is listed
+    for (uint32_t i = n4; i < n; ++i) {
+      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      if (x >= t) {
+        const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
+        if (slot < kBSurv) sm.surv[slot] = x;
+      }
+    }
+  }
   __syncthreads();
   const uint32_t ns = sm.nsurv;
   if (ns > kBSurv) return false;
@@ -382,18 +459,29 @@ __device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
   return true;
 }
 
-template <int DT>
-__device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
+template <int DT, bool VEC>
+__device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
   if (d.n <= kBSmallN) {
-    b_small<DT>(d, sm);
+    b_small<DT, VEC>(d, sm);
     return;
   }
   if (d.alpha >= 2) {
     const uint64_t S = (d.n + (1ull << d.alpha) - 1) >> d.alpha;
-    if (S <= kBMaxS && S > d.k && b_delegate<DT>(d, sm)) return;
+    if (S <= kBMaxS && S > d.k && b_delegate<DT, VEC>(d, sm)) return;
     __syncthreads();
   }
-  b_radix<DT>(d, sm);
+  b_radix<DT, VEC>(d, sm);
+}
+
+__device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
+  const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
+  if (d.dtype == DT_F32) {
+    if (vec) b_problem_v<DT_F32, true>(d, sm);
+    else b_problem_v<DT_F32, false>(d, sm);
+  } else {
+    if (vec) b_problem_v<DT_U32, true>(d, sm);
+    else b_problem_v<DT_U32, false>(d, sm);
+  }
 }
 
 // Grid: any number of workgroups of kBT threads; *counter starts at 0.
@@ -407,16 +495,25 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint32_t i = sm.item;
     if (i >= count) break;
     const BatchDesc d = descs[i];
-    if (d.dtype == DT_F32) b_problem<DT_F32>(d, sm);
-    else b_problem<DT_U32>(d, sm);
+    b_problem(d, sm);
   }
+}
+
+// Up to kBInline problems with the descriptors passed by value: no copy of
+// descriptors and no claim counter.  Grid = count: workgroup i owns problem i.
+constexpr uint32_t kBInline = 32;
+struct BatchInline {
+  BatchDesc d[kBInline];
+};
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched_inline(BatchInline b) {
+  __shared__ BatchSmem sm;
+  b_problem(b.d[blockIdx.x], sm);
 }
 
 // One problem, descriptor by value: the single-problem path for small inputs.
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_one(BatchDesc d) {
   __shared__ BatchSmem sm;
-  if (d.dtype == DT_F32) b_problem<DT_F32>(d, sm);
-  else b_problem<DT_U32>(d, sm);
+  b_problem(d, sm);
 }
 
 }  // namespace drtopk

@@ -89,7 +89,7 @@ bool batched_eligible(uint64_t n, uint32_t k);
 
 // Problems up to this size (and k <= kBMaxK) finish faster in one workgroup
 // than across the device: one launch, no workspace.
-constexpr uint64_t kOneWgMaxN = 1ull << 17;
+constexpr uint64_t kOneWgMaxN = 1ull << 16;
 
 int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P) {
   Plan p;
@@ -101,7 +101,8 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
   if (mode < 0 || mode > 3) return DRTOPK_EINVAL;
   if (mode == 3 && !batched_eligible(n, k)) return DRTOPK_EINVAL;
   if (mode == 0) {
-    if (n <= kOneWgMaxN && batched_eligible(n, k)) mode = 3;
+    // k = 1 above 2^14 keys: the delegate pass alone answers it device-wide
+    if (n <= kOneWgMaxN && batched_eligible(n, k) && !(k == 1 && n > (1u << 14))) mode = 3;
     else mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
   }
   if (mode == 3) p.alpha = batched_alpha(n, k);
@@ -137,10 +138,17 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
       const uint64_t c = (m / p.beta) * L + m;
       p.cap_c = c < n ? c : n;
     }
-    // one block per chunk: 4 MiB chunks (one round of blocks) stream best for
-    // beta = 1; beta > 1 needs the parallelism of 1 MiB chunks for its merges
-    const uint64_t cmin = p.beta == 1 ? (1ull << 20) : (1ull << 18);
-    p.chunk = cmin > 4 * L ? cmin : 4 * L;
+    // one block per chunk, about 1024 blocks: at n = 2^30 that is 4 MiB
+    // chunks (one round of blocks), which stream best for beta = 1; beta > 1
+    // needs the parallelism of 1 MiB chunks for its merges.  A chunk holds
+    // whole subranges (4 per wave) and whole unrolled wave steps.
+    const uint64_t cmax = p.beta == 1 ? (1ull << 20) : (1ull << 18);
+    const uint64_t cmin = 4 * L > 8192 ? 4 * L : 8192;
+    uint64_t c = 1;
+    while (c * 2 <= n / 1024) c *= 2;
+    if (c > cmax) c = cmax;
+    if (c < cmin) c = cmin;
+    p.chunk = c;
   }
   if (k > (uint32_t)kSmallCap) {
     uint64_t tiles = ((uint64_t)k + kSortTile - 1) / kSortTile, t2 = 1;
@@ -617,26 +625,33 @@ int batched_alpha(uint64_t n, uint32_t k) {
 bool batched_eligible(uint64_t n, uint32_t k) { return n <= kBMaxN && k <= kBMaxK; }
 
 // Enqueues one k_batched launch over `items` (already validated).
+BatchDesc make_desc(const drtopk_problem_t& q) {
+  BatchDesc d{};
+  d.keys = static_cast<const uint32_t*>(q.keys);
+  d.n = q.n;
+  d.k = q.k;
+  d.dtype = q.dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
+  d.alpha = (uint32_t)batched_alpha(q.n, q.k);
+  d.out_vals = static_cast<uint32_t*>(q.out_vals);
+  d.out_idx = q.out_idx;
+  d.out_kth = static_cast<uint32_t*>(q.out_kth);
+  return d;
+}
+
 int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_t s, Workspace* ws) {
+  if (items.size() <= kBInline) {  // descriptors as kernel arguments
+    BatchInline b{};
+    for (size_t i = 0; i < items.size(); ++i) b.d[i] = make_desc(*items[i]);
+    hipLaunchKernelGGL(k_batched_inline, dim3((unsigned)items.size()), dim3(kBT), 0, s, b);
+    return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+  }
   const size_t need = 64 + items.size() * sizeof(BatchDesc);
   int st = ensure_batch_bytes(ws, need);
   if (st) return st;
   char* h = static_cast<char*>(ws->bhost);
   std::memset(h, 0, 64);  // claim counter
   BatchDesc* hd = reinterpret_cast<BatchDesc*>(h + 64);
-  for (size_t i = 0; i < items.size(); ++i) {
-    const drtopk_problem_t& q = *items[i];
-    BatchDesc d{};
-    d.keys = static_cast<const uint32_t*>(q.keys);
-    d.n = q.n;
-    d.k = q.k;
-    d.dtype = q.dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
-    d.alpha = (uint32_t)batched_alpha(q.n, q.k);
-    d.out_vals = static_cast<uint32_t*>(q.out_vals);
-    d.out_idx = q.out_idx;
-    d.out_kth = static_cast<uint32_t*>(q.out_kth);
-    hd[i] = d;
-  }
+  for (size_t i = 0; i < items.size(); ++i) hd[i] = make_desc(*items[i]);
   if (hipMemcpyAsync(ws->bdev, ws->bhost, need, hipMemcpyHostToDevice, s) != hipSuccess) return DRTOPK_EDEVICE;
   if (hipEventRecord(ws->bev, s) != hipSuccess) return DRTOPK_EDEVICE;
   ws->bev_pending = true;

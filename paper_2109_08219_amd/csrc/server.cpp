@@ -5,9 +5,11 @@
 // any thread.  One dispatcher thread per server:
 //   * completes launches whose event has fired (latency = completion seen on
 //     the host - arrival), releasing their HBM footprint;
-//   * when a launch stream is free, admits queued requests in arrival order
-//     while the in-flight footprint stays within the budget, and launches
-//     everything admitted as one batched call on that stream;
+//   * when a launch stream is free, takes the oldest queued request: one too
+//     large for a workgroup (n > 2^22 or k > 2048) runs alone through the
+//     single-problem path; otherwise the queued small requests are admitted in
+//     arrival order while the in-flight footprint stays within the budget and
+//     launched as one batched call on that stream;
 //   * otherwise polls the busy streams, or sleeps until a request arrives.
 // Requests that arrive while batches run join the next launch on another
 // stream, so their work overlaps on the device with the running batches.
@@ -39,6 +41,7 @@ double us_between(Clock::time_point a, Clock::time_point b) {
 struct Req {
   drtopk_problem_t p{};
   uint64_t fp = 0;
+  bool large = false;  // runs alone through the single-problem path
   Clock::time_point arrival{};
   double latency_us = 0;
   int status = DRTOPK_OK;
@@ -62,7 +65,7 @@ struct drtopk_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Req> reqs;        // every request of the server's life, indexed by ticket
   uint64_t drained = 0;        // requests before this ticket were reported by a drain
-  std::deque<uint64_t> queue;  // submitted, not yet admitted
+  std::deque<uint64_t> qsmall, qlarge;  // submitted, not yet admitted, in arrival order
   std::vector<Slot> slots;
   uint64_t inflight_bytes = 0, max_inflight_bytes = 0;
   uint64_t launches = 0, launched_items = 0;
@@ -71,6 +74,7 @@ struct drtopk_server {
   std::thread th;
 
   Req& at(uint64_t t) { return reqs[t]; }
+  bool queued() const { return !qsmall.empty() || !qlarge.empty(); }
   void loop();
   bool complete_ready();
 };
@@ -119,15 +123,19 @@ void drtopk_server::loop() {
     uint64_t bytes = 0;
     {
       std::unique_lock<std::mutex> g(mu);
-      if (stop && queue.empty() && !busy) return;
-      if (free_slot && !queue.empty()) {
-        while (!queue.empty() && take.size() < cfg.max_batch) {
-          Req& r = at(queue.front());
+      if (stop && !queued() && !busy) return;
+      if (free_slot && queued()) {
+        // the oldest request decides: a large one runs alone, else a batch of small ones
+        const bool large_first = !qlarge.empty() && (qsmall.empty() || qlarge.front() < qsmall.front());
+        std::deque<uint64_t>& q = large_first ? qlarge : qsmall;
+        const uint32_t cap = large_first ? 1u : cfg.max_batch;
+        while (!q.empty() && take.size() < cap) {
+          Req& r = at(q.front());
           // admission by footprint; a request larger than the budget runs alone
           if (inflight_bytes + bytes + r.fp > cfg.hbm_budget && (inflight_bytes + bytes) > 0) break;
           bytes += r.fp;
-          take.push_back(queue.front());
-          queue.pop_front();
+          take.push_back(q.front());
+          q.pop_front();
         }
         if (!take.empty()) {
           inflight_bytes += bytes;
@@ -136,7 +144,7 @@ void drtopk_server::loop() {
       }
       if (take.empty()) {
         if (!busy) {
-          cv_work.wait(g, [&] { return stop || !queue.empty(); });
+          cv_work.wait(g, [&] { return stop || queued(); });
           continue;
         }
       }
@@ -152,7 +160,7 @@ void drtopk_server::loop() {
     }
     int st = DRTOPK_OK;
     std::vector<int> each(take.size(), DRTOPK_OK);
-    if (cfg.plain) {
+    if (cfg.plain || take.size() == 1) {  // one request: the single-problem path directly
       for (size_t i = 0; i < batch.size(); ++i) {
         const drtopk_problem_t& p = batch[i];
         each[i] = p.out_vals ? topk_select(p.keys, p.n, p.k, (int)p.dtype, p.out_vals, p.out_idx, free_slot->stream)
@@ -233,9 +241,13 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
   int st = drtopk_footprint(req->n, req->k, (int)req->dtype, &fp);
   if (st) return st;
   if (!req->keys) return DRTOPK_EINVAL;
+  int32_t route = 0, alpha = 0;
+  st = drtopk_batched_alpha(req->n, req->k, &route, &alpha);
+  if (st) return st;
   Req r;
   r.p = *req;
   r.fp = fp;
+  r.large = route == 0;
   r.arrival = arrival;
   {
     std::lock_guard<std::mutex> g(s->mu);
@@ -243,7 +255,7 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
     try {
       s->reqs.push_back(r);
       *ticket = s->reqs.size() - 1;
-      s->queue.push_back(*ticket);
+      (r.large ? s->qlarge : s->qsmall).push_back(*ticket);
     } catch (...) {
       return DRTOPK_ENOMEM;
     }
@@ -274,7 +286,7 @@ int drtopk_server_drain(drtopk_server_t* s) {
   if (!s) return DRTOPK_EINVAL;
   std::unique_lock<std::mutex> g(s->mu);
   s->cv_done.wait(g, [&] {
-    if (!s->queue.empty()) return false;
+    if (s->queued()) return false;
     for (const auto& sl : s->slots)
       if (sl.busy) return false;
     return true;

@@ -36,8 +36,8 @@ def test_planner():
     p = drt.plan(2 ** 30, 131072)
     assert p.mode == 1 and p.beta == 2 and p.alpha == 10  # beta = 2 shifts Rule 4's alpha by 2
     # small inputs and large k/n fall back to a plain radix select
-    assert drt.plan(4096, 7).mode == 3  # one workgroup (n <= 2^17, k <= 2048)
-    assert drt.plan(1 << 17, 2048).mode == 3 and drt.plan((1 << 17) + 1, 2048).mode == 1
+    assert drt.plan(4096, 7).mode == 3  # one workgroup (n <= 2^16, k <= 2048)
+    assert drt.plan(1 << 16, 2048).mode == 3 and drt.plan((1 << 16) + 1, 2048).mode == 1
     assert drt.plan(4096, 2049).mode == 2
     assert drt.plan(10 ** 6, 10 ** 5).mode == 2
 
