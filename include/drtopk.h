@@ -86,8 +86,10 @@ typedef struct {
  * launch, one workgroup per problem at a time, largest first (the delegate
  * method of Sections 4-5 inside the workgroup's LDS); larger ones run one
  * after another through the single-problem path, on the same stream.  Any
- * invalid descriptor fails the whole call with DRTOPK_EINVAL before any work
- * is enqueued.  Output buffers of different problems must not overlap. */
+ * invalid descriptor, or count >= 2^24, fails the whole call with
+ * DRTOPK_EINVAL before any work is enqueued.  Problems of more than 2^18 keys
+ * on the delegate route have their delegate vector built by several
+ * workgroups.  Output buffers of different problems must not overlap. */
 int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream);
 
 /* Autotuner table (Rule 4's subrange size and Rule 3's beta, measured rather

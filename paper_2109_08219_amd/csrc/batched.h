@@ -32,6 +32,8 @@ constexpr uint64_t kBMaxN = 1ull << 22;   // largest n handled in a workgroup
 constexpr int kBU = 8;                    // 1 KiB wave loads in flight per wave step
 constexpr uint32_t kBStep = 256 * kBU;    // keys per wave step
 constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 for gfx9-family raw buffers
+constexpr uint32_t kBTileLog = 18;        // a split problem's delegate vector is built in tiles of
+                                          // 2^max(kBTileLog, alpha) keys, one workgroup each
 
 // One problem as the kernel sees it (64 bytes).
 struct BatchDesc {
@@ -40,11 +42,11 @@ struct BatchDesc {
   uint32_t k;
   uint32_t dtype;
   uint32_t alpha;  // subrange exponent, >= 2; 0 = radix select without delegates
-  uint32_t pad;
+  uint32_t tiles;  // > 1: the delegate vector is built by this many workgroups
   uint32_t* out_vals;
   uint32_t* out_idx;
   uint32_t* out_kth;
-  uint64_t pad2;
+  uint64_t doff;   // tiles > 1: offset of the problem's delegate vector in the global buffer
 };
 static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
 
@@ -308,15 +310,20 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
   b_sort_write<DT>(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth);
 }
 
-// Delegate vector for subranges of at least 256 keys: waves stream the keys
-// in steps of kBStep with kBU 1 KiB loads in flight; each 256-key block lies
-// inside one subrange, whose delegate takes the block's maximum by an LDS
-// atomic max (D starts at 0, below every composite of a real element).
+// Delegate vector for subranges of at least 256 keys, over the keys
+// [lo, min(hi, n4)) (lo a multiple of kBStep and of 2^alpha): waves stream
+// them in steps of kBStep with kBU 1 KiB loads in flight; each 256-key block
+// lies inside one subrange, whose delegate (sm.D[s - lo / 2^alpha]) takes the
+// block's maximum by an LDS atomic max (D starts at 0, below every composite
+// of a real element).
 template <int DT, bool VEC>
-__device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, BatchSmem& sm) {
+__device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4, uint32_t alpha,
+                                        BatchSmem& sm) {
   const uint32_t L = 1u << alpha;
+  const uint32_t end = hi < n4 ? hi : n4;
+  const uint32_t s0 = lo >> alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
+  for (uint32_t base = lo + wave * kBStep; base < end; base += kBWaves * kBStep) {
     uint32_t v[kBU][4];
 #pragma unroll
     for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
@@ -328,10 +335,10 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t n4, uint32
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(enc<DT>(v[j][c]), p);
-          if (p < n4 && x > m) m = x;
+          if (p < end && x > m) m = x;
         }
       m = wave_max64(m);
-      if (lane == 0) atomicMax((unsigned long long*)&sm.D[base >> alpha], (unsigned long long)m);
+      if (lane == 0) atomicMax((unsigned long long*)&sm.D[(base >> alpha) - s0], (unsigned long long)m);
     } else {
 #pragma unroll
       for (int j = 0; j < kBU; ++j) {
@@ -340,13 +347,28 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t n4, uint32
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(enc<DT>(v[j][c]), p);
-          if (p < n4 && x > m) m = x;
+          if (p < end && x > m) m = x;
         }
         m = wave_max64(m);
-        if (lane == 0 && base + j * 256 < n4)
-          atomicMax((unsigned long long*)&sm.D[(base + j * 256) >> alpha], (unsigned long long)m);
+        if (lane == 0 && base + j * 256 < end)
+          atomicMax((unsigned long long*)&sm.D[((base + j * 256) >> alpha) - s0], (unsigned long long)m);
       }
     }
+  }
+}
+
+// The last n mod 4 keys (16-byte loads stop at n4), all in one subrange:
+// one thread folds them into its delegate sm.D[n4 / 2^alpha - s0].
+template <int DT>
+__device__ __forceinline__ void b_delegates_tail(const BatchDesc& d, uint32_t n4, uint32_t s0, BatchSmem& sm) {
+  const uint32_t n = (uint32_t)d.n;
+  if (threadIdx.x == 0 && n4 < n) {
+    uint64_t m = 0;
+    for (uint32_t i = n4; i < n; ++i) {
+      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      m = x > m ? x : m;
+    }
+    atomicMax((unsigned long long*)&sm.D[(n4 >> d.alpha) - s0], (unsigned long long)m);
   }
 }
 
@@ -411,26 +433,14 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
   }
 }
 
-// The delegate method for one problem; false if the survivors overflow LDS
-// (nothing has been written then).
+// Everything after the delegate vector (complete in sm.D[0..S)): t, the
+// qualifying subranges, the survivors and the output.  False if the survivors
+// overflow LDS (nothing has been written then).
 template <int DT, bool VEC>
-__device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
+__device__ inline bool b_finish(const BatchDesc& d, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
   const Keys<VEC> ks(d.keys, n4);
-  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
-  __syncthreads();
-  if (alpha >= 8) b_delegates_wide<DT, VEC>(ks, n4, alpha, sm);
-  else b_delegates_narrow<DT, VEC>(ks, n4, alpha, sm);
-  if (threadIdx.x == 0 && n4 < n) {  // the last n mod 4 keys, all in one subrange
-    uint64_t m = 0;
-    for (uint32_t i = n4; i < n; ++i) {
-      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
-      m = x > m ? x : m;
-    }
-    atomicMax((unsigned long long*)&sm.D[n4 >> alpha], (unsigned long long)m);
-  }
-  __syncthreads();
   if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[n4 >> alpha] : 0;
   const uint64_t t = lds_select(sm.D, S, k, sm);  // Rule 2: the k-th delegate
   // the k-1 subranges whose delegate ranks above t (order irrelevant)
@@ -459,6 +469,34 @@ __device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
   return true;
 }
 
+// The delegate method for one problem in one workgroup; false if the
+// survivors overflow LDS (nothing has been written then).
+template <int DT, bool VEC>
+__device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
+  const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
+  const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
+  const Keys<VEC> ks(d.keys, n4);
+  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
+  __syncthreads();
+  if (alpha >= 8) b_delegates_wide<DT, VEC>(ks, 0, n, n4, alpha, sm);
+  else b_delegates_narrow<DT, VEC>(ks, n4, alpha, sm);
+  b_delegates_tail<DT>(d, n4, 0, sm);
+  __syncthreads();
+  return b_finish<DT, VEC>(d, sm);
+}
+
+__device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile `tile` of a split problem (alpha >= 8): this workgroup builds the
+// delegates of its tile and publishes them to Dg with coherent stores, then
+// counts itself in; the workgroup that arrives last loads the whole delegate
+// vector and finishes the problem (radix select over the keys if its
+// survivors overflow).  Nobody waits for anybody.
+template <int DT, bool VEC>
+__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm);
+
 template <int DT, bool VEC>
 __device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
   if (d.n <= kBSmallN) {
@@ -473,6 +511,34 @@ __device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
   b_radix<DT, VEC>(d, sm);
 }
 
+template <int DT, bool VEC>
+__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
+  const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
+  const uint32_t tlog = alpha > kBTileLog ? alpha : kBTileLog;
+  const uint32_t lo = tile << tlog;
+  const uint32_t hi = n - lo > (1u << tlog) ? lo + (1u << tlog) : n;
+  const uint32_t s0 = lo >> alpha;
+  const uint32_t ns = ((hi - lo) + (1u << alpha) - 1) >> alpha;  // subranges of this tile
+  const Keys<VEC> ks(d.keys, n4);
+  for (uint32_t i = threadIdx.x; i < ns; i += kBT) sm.D[i] = 0;
+  __syncthreads();
+  b_delegates_wide<DT, VEC>(ks, lo, hi, n4, alpha, sm);
+  if (hi == n) b_delegates_tail<DT>(d, n4, s0, sm);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < ns; i += kBT) st_coh64(&Dg[d.doff + s0 + i], sm.D[i]);
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) sm.item = atomicAdd(arrive, 1u) == d.tiles - 1 ? 1u : 0u;
+  __syncthreads();
+  if (!sm.item) return;
+  const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
+  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
+  __syncthreads();
+  if (b_finish<DT, VEC>(d, sm)) return;
+  __syncthreads();
+  b_radix<DT, VEC>(d, sm);
+}
+
 __device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
   if (d.dtype == DT_F32) {
@@ -484,18 +550,38 @@ __device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
   }
 }
 
-// Grid: any number of workgroups of kBT threads; *counter starts at 0.
+__device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
+  const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
+  if (d.dtype == DT_F32) {
+    if (vec) b_tile<DT_F32, true>(d, tile, arrive, Dg, sm);
+    else b_tile<DT_F32, false>(d, tile, arrive, Dg, sm);
+  } else {
+    if (vec) b_tile<DT_U32, true>(d, tile, arrive, Dg, sm);
+    else b_tile<DT_U32, false>(d, tile, arrive, Dg, sm);
+  }
+}
+
+// Work items (problem << 8 | tile), claimed from *counter (starts at 0):
+// a problem with tiles <= 1 is one item and runs whole in the workgroup; a
+// split problem is `tiles` items whose workgroups share its delegate vector
+// through Dg, with arrive[problem] (starts at 0) counting finished tiles.
+// Any grid size works: no workgroup waits for another.
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(
-    const BatchDesc* __restrict__ descs, uint32_t count, uint32_t* counter) {
+    const BatchDesc* __restrict__ descs, const uint32_t* __restrict__ items, uint32_t nitems, uint32_t* counter,
+    uint32_t* arrive, uint64_t* Dg) {
   __shared__ BatchSmem sm;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) sm.item = atomicAdd(counter, 1u);
     __syncthreads();
-    const uint32_t i = sm.item;
-    if (i >= count) break;
+    const uint32_t w = sm.item;
+    __syncthreads();
+    if (w >= nitems) break;
+    const uint32_t it = items[w];
+    const uint32_t i = it >> 8;
     const BatchDesc d = descs[i];
-    b_problem(d, sm);
+    if (d.tiles > 1) b_tile_any(d, it & 0xFFu, &arrive[i], Dg, sm);
+    else b_problem(d, sm);
   }
 }
 

@@ -235,8 +235,9 @@ int ensure_bytes(Workspace* ws, size_t need) {
 }
 
 // Called with ws->mu held: room for `need` bytes of batch descriptors on both
-// sides; the pinned buffer is free to overwrite on return.
-int ensure_batch_bytes(Workspace* ws, size_t need) {
+// sides and `dev_need` >= need bytes on the device; the pinned buffer is free
+// to overwrite on return.
+int ensure_batch_bytes(Workspace* ws, size_t need, size_t dev_need) {
   if (ws->bev_pending) {
     if (hipEventSynchronize(ws->bev) != hipSuccess) return DRTOPK_EDEVICE;
     ws->bev_pending = false;
@@ -245,18 +246,18 @@ int ensure_batch_bytes(Workspace* ws, size_t need) {
     ws->bev = nullptr;
     return DRTOPK_EDEVICE;
   }
-  if (ws->bdev_bytes < need) {
+  if (ws->bdev_bytes < dev_need) {
     if (ws->bdev) {
       if (hipFree(ws->bdev) != hipSuccess) return DRTOPK_EDEVICE;
       ws->bdev = nullptr;
       ws->bdev_bytes = 0;
     }
-    if (hipMalloc(&ws->bdev, need) != hipSuccess) {
+    if (hipMalloc(&ws->bdev, dev_need) != hipSuccess) {
       (void)hipGetLastError();
       ws->bdev = nullptr;
       return DRTOPK_ENOMEM;
     }
-    ws->bdev_bytes = need;
+    ws->bdev_bytes = dev_need;
   }
   if (ws->bhost_bytes < need) {
     if (ws->bhost) {
@@ -638,30 +639,70 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
   return d;
 }
 
+// Tiles of a problem's delegate vector (one workgroup each): problems of
+// more than 2^kBTileLog keys on the delegate route with subranges of at
+// least 256 keys are split so several workgroups stream them.
+uint32_t batched_tiles(const BatchDesc& d) {
+  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 8) return 1;
+  const uint32_t tlog = d.alpha > kBTileLog ? d.alpha : kBTileLog;
+  return (uint32_t)((d.n + (1ull << tlog) - 1) >> tlog);
+}
+
+size_t align64(size_t x) { return (x + 63) & ~(size_t)63; }
+
+// Device layout of a staged launch: claim counter | descriptors | per-problem
+// arrival counters | work items | delegate vectors of split problems (device
+// only).  Everything before the delegate vectors is copied from the pinned
+// buffer, counters zeroed.
 int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_t s, Workspace* ws) {
-  if (items.size() <= kBInline) {  // descriptors as kernel arguments
+  std::vector<BatchDesc> descs(items.size());
+  bool split = false;
+  uint64_t dg_entries = 0;
+  size_t nwork = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    descs[i] = make_desc(*items[i]);
+    descs[i].tiles = batched_tiles(descs[i]);
+    if (descs[i].tiles > 1) {
+      split = true;
+      descs[i].doff = dg_entries;
+      dg_entries += (descs[i].n + (1ull << descs[i].alpha) - 1) >> descs[i].alpha;
+    }
+    nwork += descs[i].tiles;
+  }
+  if (items.size() <= kBInline && !split) {  // descriptors as kernel arguments
     BatchInline b{};
-    for (size_t i = 0; i < items.size(); ++i) b.d[i] = make_desc(*items[i]);
+    for (size_t i = 0; i < items.size(); ++i) b.d[i] = descs[i];
     hipLaunchKernelGGL(k_batched_inline, dim3((unsigned)items.size()), dim3(kBT), 0, s, b);
     return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
   }
-  const size_t need = 64 + items.size() * sizeof(BatchDesc);
-  int st = ensure_batch_bytes(ws, need);
+  const size_t off_desc = 64;
+  const size_t off_arrive = align64(off_desc + items.size() * sizeof(BatchDesc));
+  const size_t off_items = align64(off_arrive + items.size() * 4);
+  const size_t need = align64(off_items + nwork * 4);
+  const size_t off_dg = (need + 255) & ~(size_t)255;
+  const size_t dev_need = off_dg + (size_t)dg_entries * 8;
+  int st = ensure_batch_bytes(ws, need, dev_need);
   if (st) return st;
   char* h = static_cast<char*>(ws->bhost);
-  std::memset(h, 0, 64);  // claim counter
-  BatchDesc* hd = reinterpret_cast<BatchDesc*>(h + 64);
-  for (size_t i = 0; i < items.size(); ++i) hd[i] = make_desc(*items[i]);
+  std::memset(h, 0, off_desc);  // claim counter
+  std::memcpy(h + off_desc, descs.data(), descs.size() * sizeof(BatchDesc));
+  std::memset(h + off_arrive, 0, off_items - off_arrive);
+  uint32_t* work = reinterpret_cast<uint32_t*>(h + off_items);
+  size_t w = 0;
+  for (size_t i = 0; i < descs.size(); ++i)  // longest first; a split problem's tiles adjacent
+    for (uint32_t t = 0; t < descs[i].tiles; ++t) work[w++] = ((uint32_t)i << 8) | t;
   if (hipMemcpyAsync(ws->bdev, ws->bhost, need, hipMemcpyHostToDevice, s) != hipSuccess) return DRTOPK_EDEVICE;
   if (hipEventRecord(ws->bev, s) != hipSuccess) return DRTOPK_EDEVICE;
   ws->bev_pending = true;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t slots = 2 * (size_t)cus;  // two workgroups fit a CU's LDS and registers
-  const unsigned grid = (unsigned)(items.size() < slots ? items.size() : slots);
-  hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, s,
-                     reinterpret_cast<const BatchDesc*>(static_cast<char*>(ws->bdev) + 64), (uint32_t)items.size(),
-                     static_cast<uint32_t*>(ws->bdev));
+  const unsigned grid = (unsigned)(nwork < slots ? nwork : slots);
+  char* dv = static_cast<char*>(ws->bdev);
+  hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, s, reinterpret_cast<const BatchDesc*>(dv + off_desc),
+                     reinterpret_cast<const uint32_t*>(dv + off_items), (uint32_t)nwork,
+                     reinterpret_cast<uint32_t*>(dv), reinterpret_cast<uint32_t*>(dv + off_arrive),
+                     reinterpret_cast<uint64_t*>(dv + off_dg));
   if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
   return DRTOPK_OK;
 }
@@ -733,6 +774,7 @@ int kth_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_kt
 
 int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream) {
   if (count && !problems) return DRTOPK_EINVAL;
+  if (count >= (1u << 24)) return DRTOPK_EINVAL;  // work items carry the problem index in 24 bits
   for (uint32_t i = 0; i < count; ++i) {
     const drtopk_problem_t& q = problems[i];
     if (!q.out_vals && !q.out_kth) return DRTOPK_EINVAL;

@@ -21,11 +21,14 @@
 // coherent (sc1) stores/loads only.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace drtopk {
 
 constexpr int kTailThreads = 512;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 constexpr uint32_t kSpinLimit = 1u << 20;  // ~1 s of polling, then give up and flag
 
 struct TailArgs {
@@ -483,7 +486,50 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     const uint32_t nchunks = (uint32_t)((a.S + kQChunk - 1) / kQChunk);
     uint32_t mine = 0;
     uint32_t c = 0, sub = 8;
+    if constexpr (BETA <= 2) {
+      // every delegate of the claim's 8 x kTailThreads subranges is loaded
+      // before any is tested (16 loads in flight per thread)
+      using DV = typename std::conditional<BETA == 1, uint32_t, u32x2>::type;
+      for (;;) {
+        c = claim(&ph[PH_Q], nchunks, sm);
+        if (c >= nchunks) break;
+        ++mine;
+        DV dk[8], di[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)i * kTailThreads + threadIdx.x;
+          const uint64_t sc = s < a.S ? s : 0;
+          dk[i] = reinterpret_cast<const DV*>(a.dkey)[sc];
+          di[i] = reinterpret_cast<const DV*>(a.didx)[sc];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)i * kTailThreads + threadIdx.x;
+          const bool ok = s < a.S;
+          uint32_t kk[BETA], ii[BETA];
+          if constexpr (BETA == 1) {
+            kk[0] = dk[i];
+            ii[0] = di[i];
+          } else {
+            kk[0] = dk[i].x; kk[1] = dk[i].y;
+            ii[0] = di[i].x; ii[1] = di[i].y;
+          }
+          const bool scan = ok && ii[BETA - 1] != kInvalid && comp(kk[BETA - 1], ii[BETA - 1]) > T;
+          stage_push(sm.u.st.sq, scan, (uint32_t)s, 0u);
+#pragma unroll
+          for (int j = 0; j < BETA; ++j) {
+            const bool take = ok && !scan && ii[j] != kInvalid && comp(kk[j], ii[j]) >= T;
+            mm_add(mm, take, comp(kk[j], ii[j]));
+            stage_push(sm.u.st.sc, take, kk[j], ii[j]);
+          }
+          stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
+          stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * BETA);
+        }
+      }
+      sub = 0;
+    }
     for (;;) {
+      if constexpr (BETA <= 2) break;
       if (sub == 8) {
         c = claim(&ph[PH_Q], nchunks, sm);
         if (c >= nchunks) break;
@@ -537,6 +583,43 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       const uint32_t ch = claim(&ph[PH_S], nchunks, sm);
       if (ch >= nchunks) break;
       ++mine;
+      if (VEC && a.alpha >= 2) {
+        // queue lookups for the whole claim, then every key load, then the tests
+        constexpr int kSteps = kSChunk / (kTailThreads * 4);
+        uint64_t pp[kSteps];
+#pragma unroll
+        for (int jj = 0; jj < kSteps; ++jj) {
+          const uint64_t e = (uint64_t)ch * kSChunk + (uint64_t)jj * kTailThreads * 4 + threadIdx.x * 4;
+          pp[jj] = e < total ? ((uint64_t)ld_coh(&a.Q[e >> a.alpha]) << a.alpha) + (e & lmask) : a.n;
+        }
+        bool full = true;
+#pragma unroll
+        for (int jj = 0; jj < kSteps; ++jj) full = full && pp[jj] + 4 <= a.n;
+        uint32_t vv[kSteps][4];
+        if (__all(full)) {
+#pragma unroll
+          for (int jj = 0; jj < kSteps; ++jj) load4<DT, true>(a.keys, pp[jj], vv[jj]);
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < kSteps; ++jj)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) vv[jj][c] = pp[jj] + c < a.n ? a.keys[pp[jj] + c] : 0u;
+        }
+#pragma unroll
+        for (int jj = 0; jj < kSteps; ++jj) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint64_t pos = pp[jj] + c;
+            const uint32_t kk = enc<DT>(vv[jj][c]);
+            const uint64_t cc = comp(kk, (uint32_t)pos);
+            const bool take = pos < a.n && cc >= T;
+            mm_add(mm, take, cc);
+            stage_push(sm.u.st.sc, take, kk, (uint32_t)pos);
+          }
+          stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
+        }
+        continue;
+      }
       for (uint32_t j = 0; j < kSChunk; j += kTailThreads * 4) {
         const uint64_t e = (uint64_t)ch * kSChunk + j + threadIdx.x * 4;
         uint32_t v[4];

@@ -195,3 +195,34 @@ def test_full_workload_4096():
     say("full 4096")
     b = run_batch(hosts)
     check_batch(hosts, b, "full")
+
+
+def test_split_problems():
+    """Problems above 2^18 keys on the delegate route: several workgroups build
+    the delegate vector, the last to arrive finishes.  Ragged tails, unaligned
+    views, k-only outputs, adversarial inputs (survivor overflow after the
+    split) and repeated launches (the arrival counters restart at zero)."""
+    drt.tune_set([])
+    hosts = []
+    for i, (n, k) in enumerate([((1 << 18) + 1, 1), ((1 << 18) + 3, 7), ((1 << 19) + 2, 500), ((1 << 20) + 7, 2048),
+                                ((1 << 22) - 1, 1000), (1 << 22, 1), (3 << 19, 64)]):
+        for kind in ("uniform_u32", "normal_f32"):
+            x, dt = synth.keys(kind, n, 800 + 2 * i + (kind == "normal_f32"))
+            assert drt.batched_route(n, k)[0] == 2
+            hosts.append((x, dt, k))
+    for kind in ("sorted_f32", "heavydup_u32"):
+        x, dt = synth.keys(kind, (1 << 20) + 5, 901)
+        hosts.append((x, dt, 2048))
+    small = [h for h in workload_hosts(40, 55)]
+    allh = hosts + small
+    say("split problems", len(allh))
+    b = run_batch(allh)
+    check_batch(allh, b, "split")
+    b.run()  # second launch on the same descriptors
+    torch.cuda.synchronize()
+    check_batch(allh, b, "split repeat")
+    say("split, unaligned + k only")
+    b = run_batch(hosts, offsets=[1 + (i % 3) for i in range(len(hosts))])
+    check_batch(hosts, b, "split unaligned")
+    b = run_batch(hosts, kth_only=True)
+    check_batch(hosts, b, "split k only")
