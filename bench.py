@@ -9,8 +9,12 @@ k in {1, 1024, 131072}: six topk_select calls, sorted values + positions.
 Reported: keys/s over the whole step (value), HBM GB/s of the mandatory read
 (4 bytes per key), per-case timings, the roofline of the dominant kernel (the
 delegate pass, timed live with HIP events on its own stream), and the CPU
-oracle on a bounded sample of the same workload.  Beside the step, outside
+oracle on a bounded sample of the same workload, and a probe kernel's read
+bandwidth with the delegate pass's access pattern.  Beside the step, outside
 its timed region:
+  small    N = 2^20 uint32 uniform, k = 1024: latency;
+  adversarial  N = 2^29, k = 16384: float32 N(0,1) sorted ascending with
+           beta in {1, 2, 4, 8}, and uint32 uniform over [0, 16);
   batched  4096 independent instances (lengths log-uniform in [2^10, 2^20],
            uint32 uniform or float32 normal per instance, k uniform in
            [1, min(n, 2048)]) in one topk_select_batched call, queries/s,
@@ -22,7 +26,7 @@ its timed region:
            queries/s and p50/p99 latency (arrival -> completion on the host).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-batched] [--no-serving]
+                       [--no-adversarial] [--no-batched] [--no-serving] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -111,7 +115,65 @@ def bench_batched(drt, synth, torch, args):
             "speedup_vs_loop": ms_loop / ms, "steps": steps}
 
 
-def bench_serving(drt, synth, torch, np, pool_size=256, requests=4000):
+def _median_ms(torch, fn, reps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return {"ms_median": ts[len(ts) // 2], "ms_min": ts[0], "ms_max": ts[-1], "ms_mean": sum(ts) / len(ts)}
+
+
+def bench_small(drt, synth, torch, args):
+    """N = 2^20 uint32 uniform, k = 1024: latency (4 MiB fits the caches; no roofline)."""
+    x = synth.uniform_u32(1 << 20, synth.DEFAULT_SEED)
+    t = torch.from_numpy(x).cuda()
+    v = torch.empty(1024, dtype=t.dtype, device="cuda")
+    ix = torch.empty(1024, dtype=torch.int32, device="cuda")
+    r = _median_ms(torch, lambda: drt.topk_select(t, 1024, v, ix), max(20, args.steps), max(3, args.warmup))
+    r.update(n=1 << 20, k=1024, keys_per_s=(1 << 20) / (r["ms_median"] / 1e3), mode=drt.plan(1 << 20, 1024).mode)
+    return r
+
+
+def bench_adversarial(drt, torch, args):
+    """N = 2^29, k = 16384: float32 N(0,1) sorted ascending (beta 1, 2, 4, 8) and uint32
+    uniform over [0, 16) (planner's choice).  Inputs drawn on the GPU."""
+    print("[bench] adversarial: 2^29 keys", file=sys.stderr, flush=True)
+    n, k = 1 << 29, 16384
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20210908)
+    t = torch.randn(n, device="cuda", generator=gen)
+    t = torch.sort(t).values
+    v = torch.empty(k, dtype=t.dtype, device="cuda")
+    ix = torch.empty(k, dtype=torch.int32, device="cuda")
+    out = {"n": n, "k": k, "sorted_f32": {}}
+    for beta in (1, 2, 4, 8):
+        r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix, beta=beta), 10, 2)
+        _, _, st = drt.topk_select(t, k, v, ix, beta=beta, stats=True)
+        r.update(alpha=st.alpha, scanned=int(st.scanned), candidates=int(st.candidates),
+                 keys_per_s=n / (r["ms_median"] / 1e3))
+        out["sorted_f32"][f"beta{beta}"] = r
+    del t
+    h = torch.randint(0, 16, (n,), dtype=torch.int32, device="cuda", generator=gen).view(torch.uint32)
+    vh = torch.empty(k, dtype=h.dtype, device="cuda")
+    r = _median_ms(torch, lambda: drt.topk_select(h, k, vh, ix), 10, 2)
+    _, _, st = drt.topk_select(h, k, vh, ix, stats=True)
+    r.update(alpha=st.alpha, beta=st.beta, scanned=int(st.scanned), candidates=int(st.candidates),
+             keys_per_s=n / (r["ms_median"] / 1e3))
+    out["heavydup_u32"] = r
+    del h
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(drt, synth, torch, np, pool_size=256, requests=10000):
     """Continuous-batching server vs the per-request loop under Poisson arrivals."""
     print("[bench] serving: building the array pool", file=sys.stderr, flush=True)
     gen = torch.Generator(device="cuda")
@@ -153,6 +215,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-adversarial", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, whose HBM counters calibrate the traffic figure")
     args = ap.parse_args()
@@ -204,7 +267,11 @@ def main() -> int:
     # plan / counters of each case (outside the timed region)
     for c in cases:
         _, _, st = drt.topk_select(c["keys"], c["k"], c["vals"], c["idx"], stats=True, stream=stream)
-        c.update(alpha=st.alpha, beta=st.beta, scanned=int(st.scanned), candidates=int(st.candidates))
+        c.update(alpha=st.alpha, beta=st.beta, scanned=int(st.scanned), candidates=int(st.candidates),
+                 # the method's own traffic beyond the 4n-byte read (not counted as useful bytes):
+                 # delegate vector written, qualifying subranges re-read, survivors written
+                 overhead_bytes={"delegates": 8 * int(st.delegates), "reread": 4 * (int(st.scanned) << st.alpha),
+                                 "survivors": 8 * int(st.candidates)})
 
     # per-case latency (events around single calls)
     reps = max(3, args.steps)
@@ -222,6 +289,8 @@ def main() -> int:
         times.sort()
         c["ms_median"] = times[len(times) // 2]
         c["ms_min"] = times[0]
+        c["ms_max"] = times[-1]
+        c["ms_mean"] = sum(times) / len(times)
 
     # the timed region: K steps of all six calls
     for _ in range(args.warmup):
@@ -239,6 +308,18 @@ def main() -> int:
     t1 = time.perf_counter()
     drt.timing_enable(False)
     del_ms, tail_ms, calls = drt.timing_read()
+
+    # achievable read bandwidth of the delegate pass's access pattern (probe kernel)
+    probe_out = torch.empty(1, dtype=torch.int32, device=dev)
+    for _ in range(3):
+        drt.read_probe(t_u, probe_out, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        drt.read_probe(t_u, probe_out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    probe_GBps = 4.0 * N / (e0.elapsed_time(e1) / 20 / 1e3) / 1e9
 
     step_s = (t1 - t0) / args.steps
     keys_per_step = N * len(cases)
@@ -263,6 +344,8 @@ def main() -> int:
     case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
     del cases, t_u, t_f
     torch.cuda.empty_cache()
+    small = bench_small(drt, synth, torch, args)
+    adversarial = None if args.no_adversarial else bench_adversarial(drt, torch, args)
     batched = None if args.no_batched else bench_batched(drt, synth, torch, args)
     serving = None if args.no_serving else bench_serving(drt, synth, torch, np)
 
@@ -287,11 +370,15 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_delegate (delegate pass, 4 B/key read once)",
                      "avg_launch_us": del_avg_s * 1e6, "launches": calls,
-                     "rest_of_path_avg_us": tail_ms / calls * 1e3},
+                     "rest_of_path_avg_us": tail_ms / calls * 1e3,
+                     "probe_read_GBps": probe_GBps, "frac_of_probe": achieved / probe_GBps},
         "cpu_baseline": cpu,
+        "small_case": small,
+        "adversarial": adversarial,
         "batched": batched,
         "serving": serving,
-        "cases": [{k: c[k] for k in ("dtype", "k", "alpha", "beta", "scanned", "candidates", "ms_median", "ms_min")}
+        "cases": [{k: c[k] for k in ("dtype", "k", "alpha", "beta", "scanned", "candidates", "ms_median", "ms_min",
+                                     "ms_max", "ms_mean", "overhead_bytes")}
                   | {"keys_per_s": N / (c["ms_median"] / 1e3), "GBps": 4 * N / (c["ms_median"] / 1e3) / 1e9}
                   for c in case_rows],
     }

@@ -259,6 +259,14 @@ int drtopk_server_replay(drtopk_server_t* server, const drtopk_problem_t* reqs, 
 /* Finishes queued work, stops the dispatcher and frees the server. */
 int drtopk_server_destroy(drtopk_server_t* server);
 
+/* Measurement helper: reads keys[0 .. n - n mod 2^20) once with the delegate
+ * pass's access pattern and launch geometry (4 MiB per workgroup, 16-byte
+ * non-temporal loads, eight in flight per lane) and writes their maximum to
+ * *out_max (device).  Timing it gives the read bandwidth that pattern reaches
+ * on the device, the practical ceiling of the delegate pass.  keys 16-byte
+ * aligned, 2^20 <= n < 2^32; else DRTOPK_EINVAL. */
+int drtopk_read_probe(const void* keys, uint64_t n, uint32_t* out_max, void* stream);
+
 /* Frees the calling thread's current device's workspaces (synchronises it). */
 int drtopk_release_workspace(void);
 

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "drtopk_tune_get": [ctypes.POINTER(Tune), u32, ctypes.POINTER(u32)],
             "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
             "drtopk_footprint": [u64, u32, i32, ctypes.POINTER(u64)],
+            "drtopk_read_probe": [vp, u64, vp, vp],
             "drtopk_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "drtopk_server_submit": [vp, ctypes.POINTER(Problem), ctypes.POINTER(u64)],
             "drtopk_server_wait": [vp, u64, ctypes.POINTER(ctypes.c_double)],
@@ -422,6 +423,17 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def read_probe(keys, out=None, *, stream=None):
+    """Runs the read-bandwidth probe over keys (a 16-byte aligned device tensor of
+    4-byte elements, at least 2^20 of them); returns the 1-element output tensor."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=keys.device)
+    _check(lib().drtopk_read_probe(ctypes.c_void_p(keys.data_ptr()), keys.numel(), ctypes.c_void_p(out.data_ptr()),
+                                   _stream(stream)), "drtopk_read_probe")
+    return out
 
 
 def release_workspace() -> None:

@@ -707,6 +707,35 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
   return DRTOPK_OK;
 }
 
+// Read-bandwidth probe: the delegate pass's launch geometry (one 256-thread
+// workgroup per chunk, each wave a contiguous quarter, eight 16-byte
+// non-temporal loads in flight per lane) with only a maximum per lane, so it
+// measures what that access pattern can reach on this device.
+__global__ __launch_bounds__(256) void k_read_probe(const uint32_t* __restrict__ keys, uint64_t n, uint64_t chunk,
+                                                     uint32_t* out) {
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const uint64_t wlen = chunk >> 2;
+  const uint64_t wlo = (uint64_t)blockIdx.x * chunk + wave * wlen;
+  uint32_t m = 0;
+  if (wlo + wlen <= n) {
+    for (uint64_t j = 0; j < wlen; j += 256 * kUnroll) {
+      u32x4 v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(keys + wlo + j + u * 256 + lane * 4));
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) m = max(m, max(max(v[u].x, v[u].y), max(v[u].z, v[u].w)));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+  if (lane == 0) atomicMax(out, m);
+}
+
+__global__ void k_zero_word(uint32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
 int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   if (!stats) return DRTOPK_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
@@ -1008,6 +1037,17 @@ int drtopk_timing_read(double* delegate_ms, double* tail_ms, uint64_t* calls) {
   if (tail_ms) *tail_ms = t;
   if (calls) *calls = recs.size();
   return st;
+}
+
+int drtopk_read_probe(const void* keys, uint64_t n, uint32_t* out_max, void* stream) {
+  if (!keys || !out_max || n < (1u << 20) || n >= (1ull << 32)) return DRTOPK_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(keys) & 15u) != 0) return DRTOPK_EINVAL;
+  const uint64_t chunk = 1ull << 20;  // the beta = 1 delegate pass's chunk at n = 2^30
+  const unsigned g = (unsigned)(n / chunk);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(64), 0, s, out_max);
+  hipLaunchKernelGGL(k_read_probe, dim3(g), dim3(256), 0, s, static_cast<const uint32_t*>(keys), n, chunk, out_max);
+  return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
 }
 
 const char* drtopk_status_string(int status) {

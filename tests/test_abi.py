@@ -145,3 +145,12 @@ def test_server_and_footprint_arguments_without_gpu():
     b = ctypes.c_uint64()
     assert L.drtopk_footprint(10, 11, 0, ctypes.byref(b)) == 1
     assert L.drtopk_footprint(10, 1, 0, None) == 1
+
+
+def test_read_probe_arguments_without_gpu():
+    L = drt.lib()
+    out = ctypes.c_void_p(64)
+    assert L.drtopk_read_probe(None, 1 << 20, out, None) == 1
+    assert L.drtopk_read_probe(ctypes.c_void_p(16), (1 << 20) - 1, out, None) == 1
+    assert L.drtopk_read_probe(ctypes.c_void_p(20), 1 << 20, out, None) == 1  # not 16-byte aligned
+    assert L.drtopk_read_probe(ctypes.c_void_p(16), 1 << 20, None, None) == 1

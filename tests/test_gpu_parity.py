@@ -291,3 +291,14 @@ def test_full_size_adversarial():
     check_invariants_fast(h, fullh, 16384, "u32", to_np(vals), to_np(idx))
     # closed form: the lowest 16384 positions holding 15
     assert (to_np(idx).view(np.uint32) == np.flatnonzero(h == 15)[:16384]).all()
+
+
+def test_read_probe_reads_every_key():
+    """The bandwidth probe reads keys[0 .. n - n mod 2^20) once: its maximum
+    equals the maximum of those keys."""
+    x = synth.uniform_u32((1 << 21) + 7, 61)
+    x[12345] = 0xFFFFFFF0  # a planted maximum inside the probed range
+    x[(1 << 21) + 3] = 0xFFFFFFFF  # beyond it: not read
+    out = drt.read_probe(dev(x))
+    torch.cuda.synchronize()
+    assert int(to_np(out).view(np.uint32)[0]) == int(x[: 1 << 21].max()) == 0xFFFFFFF0
