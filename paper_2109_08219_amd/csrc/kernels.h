@@ -340,6 +340,56 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
   }
 }
 
+// beta >= 2, subranges of 256..2048 elements: a group of G = max(8, 2^alpha/64)
+// lanes owns each subrange, so a wave works on 64/G subranges at once and
+// each lane folds about 64 of a subrange's elements before the group's
+// segmented merge (log2 G steps instead of 6).  A load instruction reads
+// 64/G segments of 16*G >= 128 contiguous bytes.  The wave's range
+// [wlo, whi) starts at a subrange boundary; the caller checks that a full
+// range holds a multiple of 64/G subranges.
+template <int DT, int BETA, bool VEC>
+__device__ __forceinline__ void delegate_grouped(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                                 uint64_t wlo, uint64_t whi, bool fast, uint32_t* dkey,
+                                                 uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+  const uint32_t lane = lane_id();
+  const uint32_t L = 1u << alpha;
+  const uint32_t G = L / 64 > 8 ? L / 64 : 8;
+  const uint32_t ns = 64 / G;           // subranges per group of the wave
+  const uint32_t g = lane / G, l = lane % G;
+  const uint32_t lpl = L / (4 * G);     // 16-byte loads per lane per subrange (8 or 16)
+  const uint64_t nsub = (whi - wlo + L - 1) >> alpha;
+  for (uint64_t sb = 0; sb < nsub; sb += ns) {
+    const uint64_t s = (wlo >> alpha) + sb + g;
+    const uint64_t sbase = s << alpha;
+    const bool mine = sb + g < nsub;
+    TopB<BETA> tb;
+    tb.clear();
+    for (uint32_t i0 = 0; i0 < lpl; i0 += kUnroll) {
+      uint32_t v[kUnroll][4];
+      if (fast) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, sbase + ((uint64_t)(i0 + u) * G + l) * 4, v[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint64_t p = sbase + ((uint64_t)(i0 + u) * G + l) * 4;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[u][c] = (mine && p + c < n) ? keys[p + c] : 0u;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const uint64_t p = sbase + ((uint64_t)(i0 + u) * G + l) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (fast || (mine && p + c < n)) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
+      }
+    }
+    for (uint32_t m = 1; m < G; m <<= 1) tb.merge_xor((int)m);
+    if (l == 0 && mine && sbase < n) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
+  }
+}
+
 // Subranges of 4..128 elements: 2^(alpha-2) lanes per subrange inside each
 // 256-element wave-load; segmented butterfly merge.
 template <int DT, int BETA, bool VEC>
@@ -399,7 +449,10 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
-    if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
+    if (BETA >= 2 && gspan && wlen % gspan == 0)
+      delegate_grouped<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    else if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
     else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();

@@ -302,3 +302,25 @@ def test_read_probe_reads_every_key():
     out = drt.read_probe(dev(x))
     torch.cuda.synchronize()
     assert int(to_np(out).view(np.uint32)[0]) == int(x[: 1 << 21].max()) == 0xFFFFFFF0
+
+
+@pytest.mark.parametrize("kind", ["uniform_u32", "sorted_f32"])
+def test_grouped_lane_delegates(kind):
+    """beta >= 2 with subranges of 2^9..2^11 keys and large chunks: groups of
+    lanes own subranges (n = 2^24 + 5 so whole groups fit each wave's range;
+    the ragged tail takes the masked path).  Delegate vector and output exact."""
+    n = (1 << 24) + 5
+    x, dt = synth.keys(kind, n, 404)
+    want = {k: oracle.topk_reference(x, k, dt) for k in (1, 5000)}
+    for alpha in (9, 10, 11):
+        for beta in (2, 4):
+            say("grouped delegates", kind, alpha, beta)
+            dk, di = drt.delegates(dev(x), alpha, beta)
+            torch.cuda.synchronize()
+            got_i = to_np(di).view(np.uint32).astype(np.int64)
+            _, want_i = stages.delegates(x, dt, alpha, beta)
+            assert (got_i == want_i).all(), (kind, alpha, beta)
+            for k, (wv, wi) in want.items():
+                vals, idx = run_topk(x, k, alpha=alpha, beta=beta, mode=1)
+                assert (idx.view(np.uint32) == wi).all(), (kind, alpha, beta, k)
+                assert (vals.view(np.uint32) == wv.view(np.uint32)).all()
