@@ -765,24 +765,57 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     {
       const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
       uint32_t mine = 0;
+      // per claim: every load first; bucket counts and each element's rank in
+      // its bucket from an LDS histogram; one global reservation per nonzero
+      // bucket; then the stores
+      constexpr int kPer = kWChunk / kTailThreads;
+      constexpr int PER = kBins / kTailThreads;
+      uint32_t* lh = sm.u.st.hist;
       for (;;) {
         const uint32_t c = claim(&ph[PH_B2], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
-        for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
-          const uint32_t i = c * kWChunk + j + threadIdx.x;
+        for (int i = threadIdx.x; i < kBins; i += kTailThreads) lh[i] = 0;
+        uint32_t kk[kPer], ii[kPer], bb[kPer], rk[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
+          kk[j] = i < nc ? ld_coh(&a.ckey[i]) : 0u;
+          ii[j] = i < nc ? ld_coh(&a.cidx[i]) : 0u;
+        }
+        __syncthreads();  // histogram cleared
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
+          bb[j] = 2047u - (uint32_t)((comp(kk[j], ii[j]) - cmin) >> bsh);
+          rk[j] = i < nc ? atomicAdd(&lh[bb[j]], 1u) : 0u;
+        }
+        __syncthreads();
+        uint32_t base[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {  // reserve each bucket's range for this claim
+          const uint32_t b = threadIdx.x * PER + j;
+          const uint32_t cnt = lh[b];
+          base[j] = cnt ? ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], cnt) : 0u;
+        }
+        __syncthreads();  // every count read before it is overwritten by the base
+#pragma unroll
+        for (int j = 0; j < PER; ++j) lh[threadIdx.x * PER + j] = base[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
           if (i < nc) {
-            const uint32_t kk = ld_coh(&a.ckey[i]), ii = ld_coh(&a.cidx[i]);
-            const uint32_t b = 2047u - (uint32_t)((comp(kk, ii) - cmin) >> bsh);
-            const uint32_t slot = ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], 1u);
+            const uint32_t slot = lh[bb[j]] + rk[j];
             if (slot < a.cap_s) {
-              st_coh(&a.skey[slot], kk);
-              st_coh(&a.sidx[slot], ii);
+              st_coh(&a.skey[slot], kk[j]);
+              st_coh(&a.sidx[slot], ii[j]);
             } else {
               ctl->err |= 16u;
             }
           }
         }
+        __syncthreads();  // the bases are read before the next claim clears them
       }
       if (report(&ph[PH_B2], mine, nchunks, sm)) {
         stamp(ctl, PH_B2);
