@@ -282,6 +282,24 @@ __device__ __forceinline__ uint64_t ce_pick(uint64_t mine, uint64_t other, bool 
   return keep_max ? (mine_gt ? mine : other) : (mine_gt ? other : mine);
 }
 
+// The value of lane (lane ^ M), M a compile-time power of two below 64:
+// DPP quad permutes for 1 and 2, a DPP row rotation by 8 (within 16-lane
+// rows that is xor 8), ds_swizzle's bit-mask mode (xor inside 32-lane
+// halves, no address operand) for 4 and 16, ds_bpermute for 32.
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
+  if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (M == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+  else if constexpr (M == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+  else if constexpr (M == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+  else return (uint32_t)__shfl_xor((int)v, M);
+}
+template <int M>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v) {
+  return ((uint64_t)lane_xor32<M>((uint32_t)(v >> 32)) << 32) | lane_xor32<M>((uint32_t)v);
+}
+
 // One compare-exchange stage of block size S and partner distance J, all
 // compile-time, so the element array stays in registers.
 template <int E, uint32_t S, uint32_t J>
@@ -304,7 +322,7 @@ __device__ __forceinline__ void bs_stage(uint64_t (&v)[E], uint64_t* lds) {
     const bool lower = (lane_id() & m) == 0;
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      v[e] = ce_pick(v[e], shfl_xor64(v[e], (int)m), lower, ((threadIdx.x * E + e) & S) == 0);
+      v[e] = ce_pick(v[e], lane_xor64<(int)m>(v[e]), lower, ((threadIdx.x * E + e) & S) == 0);
   } else {
     __syncthreads();
 #pragma unroll
