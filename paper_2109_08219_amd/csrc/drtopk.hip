@@ -59,6 +59,18 @@ int rule_alpha(uint64_t n, uint32_t k) {
   return al;
 }
 
+// Rule 4's alpha, adjusted by measurement on MI355X: beta = 2 adds 2 (its
+// lane merges want longer subranges); beta = 1 on large inputs adds 1, at
+// most 13 (the delegate pass streams fastest with 2^12..2^14-key subranges:
+// n = 2^30, k = 1: 652 us at alpha 13 against 693 us at Rule 4's 16; k = 1024:
+// 707 us per call at alpha 12 against 722 us at 11).
+int planned_alpha(uint64_t n, uint32_t k, int beta) {
+  int a = rule_alpha(n, k);
+  if (beta >= 2) return a + 2;
+  if (n >= (1ull << 24)) a = a + 1 < 13 ? a + 1 : (a > 13 ? 13 : a);
+  return a;
+}
+
 int default_beta(uint64_t n, uint32_t k) {
   (void)n;
   return k <= 4096 ? 1 : 2;
@@ -116,7 +128,7 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
     if (!valid_beta(p.beta)) return DRTOPK_EINVAL;
     p.alpha = (opt && opt->alpha >= 0) ? opt->alpha
               : ta >= 0                ? ta
-                                       : rule_alpha(n, k) + (p.beta >= 2 ? 2 : 0);
+                                       : planned_alpha(n, k, p.beta);
     if (p.alpha > 24) p.alpha = 24;
     if (p.alpha > 24) return DRTOPK_EINVAL;
     const uint64_t L = 1ull << p.alpha;

@@ -299,40 +299,48 @@ constexpr int kUnroll = 8;  // 128-bit loads in flight per lane
 
 // Subranges of >= 256 elements: one wave per subrange, each lane folds its
 // elements into a private top-beta, then a butterfly merge across the wave.
+// The four waves of a block take the chunk's subranges round-robin (wave w:
+// subranges w, w+4, ...), so at any time they stream adjacent memory (a read
+// pattern about 3% faster on this device than a contiguous quarter per wave)
+// while each subrange stays inside one wave.  The chunk [clo, clo + chunk)
+// holds 4 * wlen / 2^alpha subranges; `fast`: all of it lies below n.
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
-                                              uint64_t wlo, uint64_t whi, bool fast,
+                                              uint64_t clo, uint32_t wave, uint64_t wlen, bool fast,
                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
-  const uint64_t wps_mask = (1ull << (alpha - 8)) - 1;  // wave-loads per subrange - 1
-  const uint64_t nwl = (whi + 255 - wlo) >> 8;
+  const int lw = alpha - 8;
+  const uint64_t wps_mask = (1ull << lw) - 1;  // wave-loads per subrange - 1
+  const uint64_t nwl = wlen >> 8;
+  const uint64_t first = clo + ((uint64_t)wave << alpha);
   TopB<BETA> tb;
   tb.clear();
   for (uint64_t j0 = 0; j0 < nwl; j0 += kUnroll) {
     uint32_t v[kUnroll][4];
-    if (fast) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, wlo + ((j0 + u) << 8) + lane * 4, v[u]);
-    } else {
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t j = j0 + u;
+      const uint64_t p = first + ((j >> lw) << (alpha + 2)) + ((j & wps_mask) << 8) + lane * 4;
+      if (fast) {
+        load4<DT, VEC>(keys, p, v[u]);
+      } else {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const uint64_t p = wlo + ((j0 + u) << 8) + lane * 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[u][c] = (j0 + u < nwl && p + c < n) ? keys[p + c] : 0u;
+        for (int c = 0; c < 4; ++c) v[u][c] = (j < nwl && p + c < n) ? keys[p + c] : 0u;
       }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint64_t j = j0 + u;
       if (j < nwl) {
-        const uint64_t p = wlo + (j << 8) + lane * 4;
+        const uint64_t sb = first + ((j >> lw) << (alpha + 2));
+        const uint64_t p = sb + ((j & wps_mask) << 8) + lane * 4;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
-        if (((j + 1) & wps_mask) == 0 || j + 1 == nwl) {
+        if (((j + 1) & wps_mask) == 0) {
 #pragma unroll
           for (int m = 1; m < 64; m <<= 1) tb.merge_xor(m);
-          if (lane == 0) emit_delegates<BETA>((wlo + (j << 8)) >> alpha, tb, dkey, didx, lh, bmax);
+          if (lane == 0 && sb < n) emit_delegates<BETA>(sb >> alpha, tb, dkey, didx, lh, bmax);
           tb.clear();
         }
       }
@@ -445,14 +453,16 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   __syncthreads();
   const uint32_t wave = threadIdx.x >> 6;
   const uint64_t wlen = chunk >> 2;
-  const uint64_t wlo = (uint64_t)blockIdx.x * chunk + wave * wlen;
-  if (wlo < n) {
+  const uint64_t clo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t wlo = clo + wave * wlen;
+  const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
+  const bool grouped = BETA >= 2 && gspan && wlen % gspan == 0;
+  if (alpha >= 8 && !grouped) {
+    if (clo < n) delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
+  } else if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
-    const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
-    if (BETA >= 2 && gspan && wlen % gspan == 0)
-      delegate_grouped<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
-    else if (alpha >= 8) delegate_wave<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    if (grouped) delegate_grouped<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
     else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();

@@ -29,10 +29,11 @@ def test_status_strings_and_version():
 
 
 def test_planner():
-    # Rule 4 with const = 3, rounded down, for the delegate method
-    assert drt.plan(2 ** 30, 1) == drt.Plan(1, 16, 1)
-    assert drt.plan(2 ** 30, 1024) == drt.Plan(1, 11, 1)
-    assert drt.plan(2 ** 20, 1024) == drt.Plan(1, 6, 1)
+    # Rule 4 with const = 3, rounded down, for the delegate method; on inputs of
+    # 2^24 keys and more beta = 1 takes one more, at most 13 (measured)
+    assert drt.plan(2 ** 30, 1) == drt.Plan(1, 13, 1)  # Rule 4: 16
+    assert drt.plan(2 ** 30, 1024) == drt.Plan(1, 12, 1)  # Rule 4: 11
+    assert drt.plan(2 ** 20, 1024) == drt.Plan(1, 6, 1)  # Rule 4 as is below 2^24
     p = drt.plan(2 ** 30, 131072)
     assert p.mode == 1 and p.beta == 2 and p.alpha == 10  # beta = 2 shifts Rule 4's alpha by 2
     # small inputs and large k/n fall back to a plain radix select
@@ -82,7 +83,7 @@ def test_tune_table_roundtrip_and_validation():
         # form-0 entries steer the planner, explicit options aside
         assert drt.plan(2 ** 30, 1024) == drt.Plan(1, 12, 1)
         assert drt.plan(2 ** 30, 2047) == drt.Plan(1, 12, 1)  # same floor(log2 k)
-        assert drt.plan(2 ** 30, 2048) == drt.Plan(1, 11, 1)  # no entry: Rule 4
+        assert drt.plan(2 ** 30, 2048) == drt.Plan(1, 12, 1)  # no entry: Rule 4 (11) + 1
         L = drt.lib()
         for bad in [(2, 16, 5, 9, 1), (0, 16, 5, 25, 1), (0, 16, 5, 9, 3), (0, -1, 5, 9, 1), (1, 16, 32, 9, 1)]:
             arr = (drt.Tune * 1)(drt.Tune(*bad))
