@@ -352,24 +352,25 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
 // lanes owns each subrange, so a wave works on 64/G subranges at once and
 // each lane folds about 64 of a subrange's elements before the group's
 // segmented merge (log2 G steps instead of 6).  A load instruction reads
-// 64/G segments of 16*G >= 128 contiguous bytes.  The wave's range
-// [wlo, whi) starts at a subrange boundary; the caller checks that a full
-// range holds a multiple of 64/G subranges.
+// 64/G segments of 16*G >= 128 contiguous bytes.  The chunk's batches of
+// 64/G subranges go to the four waves round-robin (adjacent memory, as in
+// delegate_wave); the caller checks that the chunk holds a multiple of
+// 4 * 64/G subranges.
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_grouped(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
-                                                 uint64_t wlo, uint64_t whi, bool fast, uint32_t* dkey,
-                                                 uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+                                                 uint64_t clo, uint32_t wave, uint64_t chunk, bool fast,
+                                                 uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint32_t L = 1u << alpha;
   const uint32_t G = L / 64 > 8 ? L / 64 : 8;
-  const uint32_t ns = 64 / G;           // subranges per group of the wave
+  const uint32_t ns = 64 / G;           // subranges per batch of the wave
   const uint32_t g = lane / G, l = lane % G;
   const uint32_t lpl = L / (4 * G);     // 16-byte loads per lane per subrange (8 or 16)
-  const uint64_t nsub = (whi - wlo + L - 1) >> alpha;
-  for (uint64_t sb = 0; sb < nsub; sb += ns) {
-    const uint64_t s = (wlo >> alpha) + sb + g;
+  const uint64_t nbatch = (chunk >> alpha) / ns;
+  for (uint64_t bi = wave; bi < nbatch; bi += 4) {
+    const uint64_t s = (clo >> alpha) + bi * ns + g;
     const uint64_t sbase = s << alpha;
-    const bool mine = sb + g < nsub;
+    const bool mine = sbase < n;
     TopB<BETA> tb;
     tb.clear();
     for (uint32_t i0 = 0; i0 < lpl; i0 += kUnroll) {
@@ -394,7 +395,7 @@ __device__ __forceinline__ void delegate_grouped(const uint32_t* __restrict__ ke
       }
     }
     for (uint32_t m = 1; m < G; m <<= 1) tb.merge_xor((int)m);
-    if (l == 0 && mine && sbase < n) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
+    if (l == 0 && mine) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
   }
 }
 
@@ -457,13 +458,15 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   const uint64_t wlo = clo + wave * wlen;
   const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
   const bool grouped = BETA >= 2 && gspan && wlen % gspan == 0;
-  if (alpha >= 8 && !grouped) {
-    if (clo < n) delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
+  if (alpha >= 8) {
+    if (clo < n) {
+      if (grouped) delegate_grouped<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, clo + chunk <= n, dkey, didx, lh, &s_bmax);
+      else delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
+    }
   } else if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
-    if (grouped) delegate_grouped<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
-    else delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
   finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax, out.on != 0);
