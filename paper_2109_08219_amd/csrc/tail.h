@@ -126,6 +126,19 @@ __device__ __forceinline__ void stage_flush_coh(Stage<CAP>& S, uint32_t* gcount,
   __syncthreads();
 }
 
+// Two stages checked behind one barrier pair; each is flushed only when
+// fewer than its margin of slots are left.  Block-uniform.
+template <int CA, int CB>
+__device__ __forceinline__ void stage_flush2_coh(Stage<CA>& A, uint32_t* acount, uint32_t acap, uint32_t* akey,
+                                                 uint32_t amargin, Stage<CB>& B, uint32_t* bcount, uint32_t bcap,
+                                                 uint32_t* bkey, uint32_t* bidx, uint32_t bmargin, Ctl* ctl) {
+  __syncthreads();
+  const uint32_t na = A.n, nb = B.n;
+  __syncthreads();
+  if (na + amargin > (uint32_t)CA) stage_flush_coh(A, acount, acap, akey, nullptr, ctl, true, 0);
+  if (nb + bmargin > (uint32_t)CB) stage_flush_coh(B, bcount, bcap, bkey, bidx, ctl, true, 0);
+}
+
 // Shared memory of the tail kernel, reused phase by phase.
 struct TailSmem {
   union {
@@ -540,8 +553,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             mm_add(mm, take, comp(kk[j], ii[j]));
             stage_push(sm.u.st.sc, take, kk[j], ii[j]);
           }
-          stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
-          stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * BETA);
+          stage_flush2_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, kTailThreads, sm.u.st.sc, &ctl->nc, ctl->cap_c,
+                           a.ckey, a.cidx, kTailThreads * BETA, ctl);
         }
       }
       sub = 0;
@@ -577,6 +590,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
       stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * BETA);
     }
+    // everything a block staged is published before it reports its chunks:
+    // a phase's completion then implies all of its output is visible
     stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, true, 0);
     stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, true, 0);
     mm_flush(mm, ctl);
