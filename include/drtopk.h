@@ -124,7 +124,7 @@ int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count);
 int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha);
 
 /* Explicit method parameters (for tests, tuning and ablations).
- *   alpha  subrange = 2^alpha elements (Section 5.1); -1 = planner's choice
+ *   alpha  subrange = 2^alpha elements (Section 5.1), at most 24; -1 = planner's choice
  *   beta   delegates per subrange (Rule 3): 1, 2, 4 or 8; 0 = planner's choice
  *   mode   0 = planner's choice, 1 = delegate method, 2 = plain radix select
  *          over V with no delegates, 3 = the whole problem in one workgroup
@@ -256,7 +256,10 @@ int drtopk_server_stats(drtopk_server_t* server, drtopk_server_stats_t* out, int
  * wall time of the whole replay to *elapsed_us (either may be NULL). */
 int drtopk_server_replay(drtopk_server_t* server, const drtopk_problem_t* reqs, const double* arrival_us,
                          uint32_t count, double* latency_us, double* elapsed_us);
-/* Finishes queued work, stops the dispatcher and frees the server. */
+/* Finishes queued work, stops the dispatcher and frees the server.  No other
+ * call on this server may run concurrently with or after it.  If the
+ * dispatcher runs out of host memory, every unfinished request completes with
+ * DRTOPK_ENOMEM and later submits return DRTOPK_ENOMEM. */
 int drtopk_server_destroy(drtopk_server_t* server);
 
 /* Measurement helper: reads keys[0 .. n - n mod 2^20) once with the delegate

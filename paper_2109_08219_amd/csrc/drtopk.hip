@@ -126,11 +126,11 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
     if (!tune_lookup(DRTOPK_FORM_SINGLE, n, k, &ta, &tb)) ta = -1, tb = 0;
     p.beta = (opt && opt->beta > 0) ? opt->beta : tb > 0 ? tb : default_beta(n, k);
     if (!valid_beta(p.beta)) return DRTOPK_EINVAL;
+    if (opt && opt->alpha > 24) return DRTOPK_EINVAL;
     p.alpha = (opt && opt->alpha >= 0) ? opt->alpha
               : ta >= 0                ? ta
                                        : planned_alpha(n, k, p.beta);
     if (p.alpha > 24) p.alpha = 24;
-    if (p.alpha > 24) return DRTOPK_EINVAL;
     const uint64_t L = 1ull << p.alpha;
     p.S = (n + L - 1) >> p.alpha;
     p.nd = p.S * (uint64_t)p.beta;

@@ -71,13 +71,45 @@ struct drtopk_server {
   uint64_t launches = 0, launched_items = 0;
   std::vector<double> lat;  // completed latencies since the last stats reset
   bool stop = false;
+  bool broken = false;      // the dispatcher failed (out of host memory): requests fail
   std::thread th;
 
   Req& at(uint64_t t) { return reqs[t]; }
   bool queued() const { return !qsmall.empty() || !qlarge.empty(); }
   void loop();
+  void run();
+  void fail_all();
   bool complete_ready();
 };
+
+// The dispatcher, with a failure path: if it cannot allocate, it waits for
+// the launches in flight and completes every unfinished request with
+// DRTOPK_ENOMEM, so no waiter blocks forever; later submits fail.
+void drtopk_server::run() {
+  try {
+    loop();
+  } catch (...) {
+    fail_all();
+  }
+}
+
+void drtopk_server::fail_all() {
+  for (auto& sl : slots) (void)hipStreamSynchronize(sl.stream);
+  std::lock_guard<std::mutex> g(mu);
+  broken = true;
+  for (auto& r : reqs)
+    if (!r.done) {
+      r.status = DRTOPK_ENOMEM;
+      r.done = true;
+    }
+  qsmall.clear();
+  qlarge.clear();
+  for (auto& sl : slots) {
+    sl.items.clear();
+    sl.busy = false;
+  }
+  cv_done.notify_all();
+}
 
 // Marks finished launches complete; returns true if any slot is still busy.
 bool drtopk_server::complete_ready() {
@@ -217,7 +249,7 @@ int drtopk_server_create(const drtopk_server_config_t* cfg, drtopk_server_t** ou
     }
   }
   try {
-    s->th = std::thread([s] { s->loop(); });
+    s->th = std::thread([s] { s->run(); });
   } catch (...) {
     for (auto& x : s->slots) {
       (void)hipEventDestroy(x.ev);
@@ -252,6 +284,7 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return DRTOPK_EINVAL;
+    if (s->broken) return DRTOPK_ENOMEM;
     try {
       s->reqs.push_back(r);
       *ticket = s->reqs.size() - 1;

@@ -1,5 +1,6 @@
-"""Autotuner for the subrange size of the batched form (Rule 4, measured).
+"""Autotuner: subrange size (Rule 4) and delegates per subrange (Rule 3), measured.
 
+Batched form:
 For every bucket (floor(log2 n), floor(log2 k)) that the batched kernel owns,
 a batch of synthetic problems of that bucket (half uint32 uniform, half
 float32 normal, lengths and k uniform inside the bucket) is timed with each
@@ -12,7 +13,12 @@ alternative beats Rule 4.  The table is written to tuning.json,
 which the binding loads when it opens the library.  Every alpha gives the
 same results; only the time changes.
 
-    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10]
+Single problems (--single): for n = 2^24 .. 2^30 and k = 2^0 .. 2^17, the
+planner's (alpha, beta) against alpha within 2 of it and beta in {1, 2, 4},
+on uint32 uniform and float32 normal keys (the sum of both times); an entry
+is written only where a candidate beats the planner by more than 2%.
+
+    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single]
 """
 from __future__ import annotations
 
@@ -101,11 +107,66 @@ def tune_batched(drt, torch, problems, reps, log=print):
     return entries
 
 
+def tune_single(drt, torch, reps, log=print):
+    entries = []
+    torch.manual_seed(20210908)
+    drt.tune_set([])
+    full_u = torch.randint(-2 ** 31, 2 ** 31, (1 << 30,), dtype=torch.int32, device="cuda").view(torch.uint32)
+    full_f = torch.randn(1 << 30, device="cuda")
+    for lg_n in (24, 26, 28, 30):
+        n = 1 << lg_n
+        keys = (full_u[:n], full_f[:n])
+        for lg_k in (0, 4, 8, 10, 12, 14, 17):
+            k = 1 << lg_k
+            base = drt.plan(n, k)
+            if base.mode != 1:
+                continue
+            vals = [torch.empty(k, dtype=t.dtype, device="cuda") for t in keys]
+            idx = torch.empty(k, dtype=torch.int32, device="cuda")
+
+            def time_opts(alpha, beta):
+                tot = 0.0
+                for t, v in zip(keys, vals):
+                    run = (lambda: drt.topk_select(t, k, v, idx)) if alpha is None else \
+                        (lambda: drt.topk_select(t, k, v, idx, alpha=alpha, beta=beta, mode=1))
+                    for _ in range(2):
+                        run()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        run()
+                    e1.record()
+                    e1.synchronize()
+                    tot += e0.elapsed_time(e1) / reps
+                return tot
+
+            cands = [(a, b) for b in (1, 2, 4) for a in range(max(2, base.alpha - 2), min(24, base.alpha + 2) + 1)]
+            times = {}
+            for _ in range(2):  # two rounds, interleaved; the faster run counts
+                for name, (a, b) in [("plan", (None, None))] + [(f"a{a}b{b}", (a, b)) for a, b in cands]:
+                    t = time_opts(a, b)
+                    times[name] = min(times.get(name, t), t)
+            best = min(times, key=times.get)
+            line = f"single n=2^{lg_n} k=2^{lg_k}: plan a{base.alpha}b{base.beta} {times['plan']:.3f} ms, best {best} {times[best]:.3f} ms"
+            if best != "plan" and times[best] < 0.98 * times["plan"]:
+                a, b = dict((f"a{a}b{b}", (a, b)) for a, b in cands)[best]
+                entries.append({"form": drt.FORM_SINGLE, "lg_n": lg_n, "lg_k": lg_k, "alpha": a, "beta": b,
+                                "ms": round(times[best], 4), "rule_alpha": base.alpha, "rule_beta": base.beta,
+                                "rule_ms": round(times["plan"], 4)})
+                line += "  -> entry"
+            log(line)
+    del full_u, full_f
+    torch.cuda.empty_cache()
+    return entries
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
     ap.add_argument("--problems", type=int, default=512)
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--single", action="store_true", help="also tune single problems (alpha, beta)")
     args = ap.parse_args(argv)
     import torch
     import paper_2109_08219_amd as drt
@@ -113,6 +174,8 @@ def main(argv=None):
         sys.exit("the autotuner measures on the GPU; none is visible")
     t0 = time.time()
     entries = tune_batched(drt, torch, args.problems, args.reps, log=lambda s: print(s, flush=True))
+    if args.single:
+        entries += tune_single(drt, torch, max(3, args.reps // 2), log=lambda s: print(s, flush=True))
     doc = {"device": torch.cuda.get_device_name(0), "problems_per_bucket": args.problems, "reps": args.reps,
            "seconds": round(time.time() - t0, 1), "entries": entries}
     with open(args.out, "w") as f:

@@ -62,6 +62,14 @@ def test_null_pointers_rejected():
     assert L.drtopk_delegates(ctypes.c_void_p(16), 10, 0, 3, 3, ctypes.c_void_p(32), ctypes.c_void_p(48), None) == 1
 
 
+@pytest.mark.parametrize("alpha,beta,mode", [(25, 1, 1), (3, 3, 1), (3, 1, 4), (3, 1, -1)])
+def test_explicit_options_validated_without_gpu(alpha, beta, mode):
+    L = drt.lib()
+    o = drt.Options(alpha, beta, mode, 0)
+    assert L.topk_select_ex(ctypes.c_void_p(16), 1 << 20, 5, 0, ctypes.c_void_p(32), None, ctypes.byref(o),
+                            None, None) == 1
+
+
 def test_batched_validates_every_problem_first():
     L = drt.lib()
     probs = (drt.Problem * 2)()
