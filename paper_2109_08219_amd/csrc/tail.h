@@ -139,6 +139,11 @@ __device__ __forceinline__ void stage_flush2_coh(Stage<CA>& A, uint32_t* acount,
   if (nb + bmargin > (uint32_t)CB) stage_flush_coh(B, bcount, bcap, bkey, bidx, ctl, true, 0);
 }
 
+// Bins of the bucket-rank sort (top 12 bits of x - min) and the fullest bin
+// it takes before it leaves the sort to the bitonic network.
+constexpr int kRankBins = 4096;
+constexpr uint32_t kRankMaxBin = 64;
+
 // Shared memory of the tail kernel, reused phase by phase.
 struct TailSmem {
   union {
@@ -150,6 +155,9 @@ struct TailSmem {
     } st;
   } u;
   uint32_t scan[kTailThreads];
+  uint32_t rbins[kRankBins + 1];  // bucket-rank sort: bin counts, then bin starts
+  uint64_t rred[2 * (kTailThreads / 64)];
+  uint32_t rwave[2 * (kTailThreads / 64)];
   uint32_t out[4];
   uint32_t item;
   int last;
@@ -383,10 +391,141 @@ __device__ __noinline__ void sort_and_write_e(const uint32_t* key, const uint32_
   }
 }
 
+// Bucket-rank sort of `count` (<= E * kTailThreads) distinct composites, read
+// coherently from (key, idx), writing the first `limit` as outputs
+// first_slot, first_slot+1, ...: no sorting network.  The composites are
+// binned by the top 12 bits of their distance from the smallest (bin 0 holds
+// the largest), counted in LDS, scattered bin by bin into `buf`, and each
+// takes the slot (start of its bin) + (number of larger composites in its
+// bin).  Work per element is its bin's size, so the sort gives up (false,
+// nothing written) when the fullest bin holds more than kRankMaxBin -- keys
+// crowded into a narrow range -- and the caller sorts by network instead.
+template <int DT, int E>
+__device__ __noinline__ bool rank_sort_write_e(const uint32_t* key, const uint32_t* idx, uint32_t count,
+                                               uint32_t first_slot, uint32_t limit, uint32_t k, uint32_t* out_vals,
+                                               uint32_t* out_idx, uint32_t* out_kth, uint64_t* buf, uint32_t* bins,
+                                               uint64_t* red, uint32_t* wred) {
+  constexpr int NT = kTailThreads, NW = NT / 64, PER = kRankBins / NT;
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+  uint64_t v[E];
+  uint64_t mx = 0, nmn = 0;  // largest composite, and the complement of the smallest
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = e * NT + t;
+    v[e] = g < count ? comp(ld_coh(&key[g]), ld_coh(&idx[g])) : 0ull;
+    if (g < count) {
+      mx = v[e] > mx ? v[e] : mx;
+      nmn = ~v[e] > nmn ? ~v[e] : nmn;
+    }
+  }
+#define DRTOPK_MAX2(M)                                     \
+  {                                                        \
+    const uint64_t a_ = lane_xor64<M>(mx), b_ = lane_xor64<M>(nmn); \
+    mx = a_ > mx ? a_ : mx;                                \
+    nmn = b_ > nmn ? b_ : nmn;                             \
+  }
+  DRTOPK_MAX2(1) DRTOPK_MAX2(2) DRTOPK_MAX2(4) DRTOPK_MAX2(8) DRTOPK_MAX2(16) DRTOPK_MAX2(32)
+#undef DRTOPK_MAX2
+  if (lane == 0) {
+    red[w] = mx;
+    red[NW + w] = nmn;
+  }
+  for (int i = t; i < kRankBins; i += NT) bins[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    mx = red[i] > mx ? red[i] : mx;
+    nmn = red[NW + i] > nmn ? red[NW + i] : nmn;
+  }
+  const uint64_t lo = ~nmn;
+  const uint32_t bits = bitlen64(mx - lo);
+  const uint32_t sh = bits > 12u ? bits - 12u : 0u;
+  uint32_t b[E], r[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = e * NT + t;
+    b[e] = (uint32_t)(kRankBins - 1) - (uint32_t)((v[e] - lo) >> sh);
+    r[e] = g < count ? atomicAdd(&bins[b[e]], 1u) : 0u;
+  }
+  __syncthreads();
+  // exclusive scan of the bin counts (PER consecutive bins per thread) and the fullest bin
+  uint32_t c[PER], sum = 0, big = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    c[j] = bins[t * PER + j];
+    sum += c[j];
+    big = c[j] > big ? c[j] : big;
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t y = __shfl_xor(big, o);
+    big = y > big ? y : big;
+  }
+  if (lane == 63) wred[w] = inc;
+  if (lane == 0) wred[NW + w] = big;
+  __syncthreads();
+  uint32_t off = inc - sum;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if ((uint32_t)i < w) off += wred[i];
+    big = wred[NW + i] > big ? wred[NW + i] : big;
+  }
+  if (big > kRankMaxBin) return false;  // block-uniform
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    bins[t * PER + j] = off;
+    off += c[j];
+  }
+  if (t == NT - 1) bins[kRankBins] = off;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (e * NT + t < count) buf[bins[b[e]] + r[e]] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e * NT + t >= count) continue;
+    const uint32_t st = bins[b[e]], en = bins[b[e] + 1];
+    uint32_t slot = st;
+    for (uint32_t j = st; j < en; ++j) slot += buf[j] > v[e] ? 1u : 0u;
+    if (slot < limit) write_out<DT>(v[e], first_slot + slot, k, out_vals, out_idx, out_kth);
+  }
+  __syncthreads();  // the caller reuses the LDS
+  return true;
+}
+
+struct RankLds {
+  uint32_t* bins;
+  uint64_t* red;
+  uint32_t* wred;
+};
+
 template <int DT>
 __device__ inline void sort_and_write(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t first_slot,
                                       uint32_t limit, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
-                                      uint32_t* out_kth, uint64_t* lds) {
+                                      uint32_t* out_kth, uint64_t* lds, const RankLds& rl) {
+  if (count > 1u * kTailThreads) {
+    bool done;
+    if (count <= 2u * kTailThreads)
+      done = rank_sort_write_e<DT, 2>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds, rl.bins,
+                                      rl.red, rl.wred);
+    else if (count <= 4u * kTailThreads)
+      done = rank_sort_write_e<DT, 4>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds, rl.bins,
+                                      rl.red, rl.wred);
+    else if (count <= 8u * kTailThreads)
+      done = rank_sort_write_e<DT, 8>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds, rl.bins,
+                                      rl.red, rl.wred);
+    else
+      done = rank_sort_write_e<DT, 16>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds,
+                                       rl.bins, rl.red, rl.wred);
+    if (done) return;
+  }
   if (count <= 1u * kTailThreads)
     sort_and_write_e<DT, 1>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
   else if (count <= 2u * kTailThreads)
@@ -425,7 +564,7 @@ __device__ __forceinline__ void mm_flush(MinMax& m, Ctl* ctl) {
 template <int DT>
 __device__ inline void small_output(const TailArgs& a, uint32_t nc, TailSmem& sm) {
   sort_and_write<DT>(a.ckey, a.cidx, nc, 0, a.k, a.k, a.kth_only ? nullptr : a.out_vals,
-                     a.kth_only ? nullptr : a.out_idx, a.out_kth, sm.u.sortbuf);
+                     a.kth_only ? nullptr : a.out_idx, a.out_kth, sm.u.sortbuf, RankLds{sm.rbins, sm.rred, sm.rwave});
 }
 
 enum { PH_H = 0, PH_Q = 1, PH_S = 2, PH_F1 = 3, PH_B1 = 4, PH_B2 = 5, PH_B3 = 6, PH_FSEL = 7, PH_FC = 13, PH_FS = 14,
@@ -874,7 +1013,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         }
         sort_and_write<DT>(a.skey + lo, a.sidx + lo, cnt, lo, a.k - lo < cnt ? a.k - lo : cnt, a.k,
                            a.kth_only ? nullptr : a.out_vals, a.kth_only ? nullptr : a.out_idx, a.out_kth,
-                           sm.u.sortbuf);
+                           sm.u.sortbuf, RankLds{sm.rbins, sm.rred, sm.rwave});
       }
       if (report(&ph[PH_B3], mine, ng, sm)) stamp(ctl, PH_B3);
     }
@@ -915,7 +1054,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     wait_ready(&ph[PH_FC], ctl);
   }
   if (claim(&ph[PH_FS], 1, sm) != 0) return;
-  sort_and_write<DT>(a.okey, a.oidx, a.k, 0, a.k, a.k, a.out_vals, a.out_idx, a.out_kth, sm.u.sortbuf);
+  sort_and_write<DT>(a.okey, a.oidx, a.k, 0, a.k, a.k, a.out_vals, a.out_idx, a.out_kth, sm.u.sortbuf,
+                     RankLds{sm.rbins, sm.rred, sm.rwave});
   stamp(ctl, PH_FS);
 }
 

@@ -13,10 +13,12 @@ alternative beats Rule 4.  The table is written to tuning.json,
 which the binding loads when it opens the library.  Every alpha gives the
 same results; only the time changes.
 
-Single problems (--single): for n = 2^24 .. 2^30 and k = 2^0 .. 2^17, the
-planner's (alpha, beta) against alpha within 2 of it and beta in {1, 2, 4},
-on uint32 uniform and float32 normal keys (the sum of both times); an entry
-is written only where a candidate beats the planner by more than 2%.
+Single problems (--single): for n = 2^20 .. 2^30 and k = 2^0 .. 2^17 where
+the planner takes the delegate method, its (alpha, beta) against alpha
+within 2 of it and beta in {1, 2, 4}, on uint32 uniform and float32 normal
+keys of n = 2^lg_n (the sum of both times; three interleaved rounds, the
+fastest run counts); an entry is written only where a candidate beats the
+planner by more than 3%.
 
     python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single]
 """
@@ -113,10 +115,10 @@ def tune_single(drt, torch, reps, log=print):
     drt.tune_set([])
     full_u = torch.randint(-2 ** 31, 2 ** 31, (1 << 30,), dtype=torch.int32, device="cuda").view(torch.uint32)
     full_f = torch.randn(1 << 30, device="cuda")
-    for lg_n in (24, 26, 28, 30):
+    for lg_n in range(20, 31):
         n = 1 << lg_n
         keys = (full_u[:n], full_f[:n])
-        for lg_k in (0, 4, 8, 10, 12, 14, 17):
+        for lg_k in range(0, 18):
             k = 1 << lg_k
             base = drt.plan(n, k)
             if base.mode != 1:
@@ -143,13 +145,13 @@ def tune_single(drt, torch, reps, log=print):
 
             cands = [(a, b) for b in (1, 2, 4) for a in range(max(2, base.alpha - 2), min(24, base.alpha + 2) + 1)]
             times = {}
-            for _ in range(2):  # two rounds, interleaved; the faster run counts
+            for _ in range(3):  # three rounds, interleaved; the fastest run counts
                 for name, (a, b) in [("plan", (None, None))] + [(f"a{a}b{b}", (a, b)) for a, b in cands]:
                     t = time_opts(a, b)
                     times[name] = min(times.get(name, t), t)
             best = min(times, key=times.get)
             line = f"single n=2^{lg_n} k=2^{lg_k}: plan a{base.alpha}b{base.beta} {times['plan']:.3f} ms, best {best} {times[best]:.3f} ms"
-            if best != "plan" and times[best] < 0.98 * times["plan"]:
+            if best != "plan" and times[best] < 0.97 * times["plan"]:
                 a, b = dict((f"a{a}b{b}", (a, b)) for a, b in cands)[best]
                 entries.append({"form": drt.FORM_SINGLE, "lg_n": lg_n, "lg_k": lg_k, "alpha": a, "beta": b,
                                 "ms": round(times[best], 4), "rule_alpha": base.alpha, "rule_beta": base.beta,

@@ -122,6 +122,25 @@ def test_candidate_stage(kind):
             assert tv < info["t"][0] or (tv == info["t"][0] and tpos >= info["t"][1])
 
 
+@pytest.mark.parametrize("kind", KINDS + ["dup4_u32"])
+def test_survivor_sort_routes(kind):
+    """Survivor counts from about 600 to 9000, sorted by one workgroup (bucket
+    rank by the top bits, or the bitonic network when keys crowd a bin: the
+    16-value heavy-duplicate input), and beyond, sorted in bucket groups by
+    many workgroups.  dup4_u32 holds each value about 4 times: bins of tied
+    keys whose order comes from the positions alone."""
+    n = (1 << 20) + 9
+    if kind == "dup4_u32":
+        x, dt = synth.heavy_dup_u32(n, 4321, distinct=1 << 18), "u32"
+    else:
+        x, dt = synth.keys(kind, n, 4321)
+    for k, alpha, beta in [(600, None, None), (1100, None, None), (2100, None, None), (4096, None, None),
+                           (4096, 7, 1), (5000, 6, 1), (7000, 5, 1), (8192, None, None), (30000, None, None)]:
+        say("survivor sort", kind, k, alpha, beta)
+        vals, idx = run_topk(x, k, alpha=alpha, beta=beta, mode=1)
+        check_exact(x, k, dt, vals, idx, f"{kind} k={k} alpha={alpha} beta={beta}")
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_tail_variants_agree(kind):
     """The cooperative tail kernel and the one-kernel-per-step tail give identical output."""
