@@ -573,6 +573,47 @@ constexpr uint32_t kWChunk = kTailThreads * 8;
 constexpr uint32_t kSChunk = kTailThreads * 4 * 8;
 constexpr uint32_t kGroup = 2048;  // output positions per sort group (a group holds < 2 kGroup)
 
+// One S-phase claim of STEPS x (kTailThreads x 4) elements of the virtual
+// concatenated vector, 16-byte aligned keys and subranges of at least 4:
+// every queue lookup first, then every key load, then the tests.
+template <int DT, int STEPS>
+__device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, uint64_t total, uint64_t T,
+                                            TailSmem& sm, MinMax& mm, Ctl* ctl) {
+  const uint64_t lmask = (1ull << a.alpha) - 1;
+  uint64_t pp[STEPS];
+#pragma unroll
+  for (int jj = 0; jj < STEPS; ++jj) {
+    const uint64_t e = first + (uint64_t)jj * kTailThreads * 4 + threadIdx.x * 4;
+    pp[jj] = e < total ? ((uint64_t)ld_coh(&a.Q[e >> a.alpha]) << a.alpha) + (e & lmask) : a.n;
+  }
+  bool full = true;
+#pragma unroll
+  for (int jj = 0; jj < STEPS; ++jj) full = full && pp[jj] + 4 <= a.n;
+  uint32_t vv[STEPS][4];
+  if (__all(full)) {
+#pragma unroll
+    for (int jj = 0; jj < STEPS; ++jj) load4<DT, true>(a.keys, pp[jj], vv[jj]);
+  } else {
+#pragma unroll
+    for (int jj = 0; jj < STEPS; ++jj)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vv[jj][c] = pp[jj] + c < a.n ? a.keys[pp[jj] + c] : 0u;
+  }
+#pragma unroll
+  for (int jj = 0; jj < STEPS; ++jj) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t pos = pp[jj] + c;
+      const uint32_t kk = enc<DT>(vv[jj][c]);
+      const uint64_t cc = comp(kk, (uint32_t)pos);
+      const bool take = pos < a.n && cc >= T;
+      mm_add(mm, take, cc);
+      stage_push(sm.u.st.sc, take, kk, (uint32_t)pos);
+    }
+    stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
+  }
+}
+
 template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   __shared__ TailSmem sm;
@@ -746,7 +787,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   {
     const uint32_t nq = ld_coh(&ctl->nq) < ctl->cap_q ? ld_coh(&ctl->nq) : ctl->cap_q;
     const uint64_t total = (uint64_t)nq << a.alpha;
-    const uint32_t nchunks = (uint32_t)((total + kSChunk - 1) / kSChunk);
+    // claims of 1..8 steps of kTailThreads x 4 elements: the largest that
+    // still gives every block a claim, so short re-reads spread over the device
+    constexpr uint32_t kStep = kTailThreads * 4;
+    uint32_t steps = kSChunk / kStep;
+    while (steps > 1 && (total + (uint64_t)steps * kStep - 1) / ((uint64_t)steps * kStep) < gridDim.x) steps >>= 1;
+    const uint32_t chunk = steps * kStep;
+    const uint32_t nchunks = (uint32_t)((total + chunk - 1) / chunk);
     const uint64_t lmask = (1ull << a.alpha) - 1;
     if (threadIdx.x == 0) sm.u.st.sc.n = 0;
     mm_init(mm);
@@ -756,44 +803,15 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       if (ch >= nchunks) break;
       ++mine;
       if (VEC && a.alpha >= 2) {
-        // queue lookups for the whole claim, then every key load, then the tests
-        constexpr int kSteps = kSChunk / (kTailThreads * 4);
-        uint64_t pp[kSteps];
-#pragma unroll
-        for (int jj = 0; jj < kSteps; ++jj) {
-          const uint64_t e = (uint64_t)ch * kSChunk + (uint64_t)jj * kTailThreads * 4 + threadIdx.x * 4;
-          pp[jj] = e < total ? ((uint64_t)ld_coh(&a.Q[e >> a.alpha]) << a.alpha) + (e & lmask) : a.n;
-        }
-        bool full = true;
-#pragma unroll
-        for (int jj = 0; jj < kSteps; ++jj) full = full && pp[jj] + 4 <= a.n;
-        uint32_t vv[kSteps][4];
-        if (__all(full)) {
-#pragma unroll
-          for (int jj = 0; jj < kSteps; ++jj) load4<DT, true>(a.keys, pp[jj], vv[jj]);
-        } else {
-#pragma unroll
-          for (int jj = 0; jj < kSteps; ++jj)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) vv[jj][c] = pp[jj] + c < a.n ? a.keys[pp[jj] + c] : 0u;
-        }
-#pragma unroll
-        for (int jj = 0; jj < kSteps; ++jj) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const uint64_t pos = pp[jj] + c;
-            const uint32_t kk = enc<DT>(vv[jj][c]);
-            const uint64_t cc = comp(kk, (uint32_t)pos);
-            const bool take = pos < a.n && cc >= T;
-            mm_add(mm, take, cc);
-            stage_push(sm.u.st.sc, take, kk, (uint32_t)pos);
-          }
-          stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
-        }
+        const uint64_t first = (uint64_t)ch * chunk;
+        if (steps == 8) s_claim_vec<DT, 8>(a, first, total, T, sm, mm, ctl);
+        else if (steps == 4) s_claim_vec<DT, 4>(a, first, total, T, sm, mm, ctl);
+        else if (steps == 2) s_claim_vec<DT, 2>(a, first, total, T, sm, mm, ctl);
+        else s_claim_vec<DT, 1>(a, first, total, T, sm, mm, ctl);
         continue;
       }
-      for (uint32_t j = 0; j < kSChunk; j += kTailThreads * 4) {
-        const uint64_t e = (uint64_t)ch * kSChunk + j + threadIdx.x * 4;
+      for (uint32_t j = 0; j < chunk; j += kStep) {
+        const uint64_t e = (uint64_t)ch * chunk + j + threadIdx.x * 4;
         uint32_t v[4];
         uint64_t pos[4];
         bool in[4];
