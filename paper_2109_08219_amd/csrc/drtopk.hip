@@ -71,9 +71,11 @@ int planned_alpha(uint64_t n, uint32_t k, int beta) {
   return a;
 }
 
+// Two delegates per subrange pay off for large k on large inputs only
+// (measured on MI355X: at n <= 2^24 and k = 2^13..2^17, beta = 1 at Rule 4's
+// alpha is 15-29% faster than beta = 2).
 int default_beta(uint64_t n, uint32_t k) {
-  (void)n;
-  return k <= 4096 ? 1 : 2;
+  return (k <= 4096 || n < (1ull << 25)) ? 1 : 2;
 }
 
 bool valid_beta(int b) { return b == 1 || b == 2 || b == 4 || b == 8; }

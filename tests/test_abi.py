@@ -28,7 +28,15 @@ def test_status_strings_and_version():
     assert "gfx950" in drt.version()
 
 
-def test_planner():
+@pytest.fixture
+def no_tuning():
+    saved = drt.tune_get()
+    drt.tune_set([])
+    yield
+    drt.tune_set(saved)
+
+
+def test_planner(no_tuning):
     # Rule 4 with const = 3, rounded down, for the delegate method; on inputs of
     # 2^24 keys and more beta = 1 takes one more, at most 13 (measured)
     assert drt.plan(2 ** 30, 1) == drt.Plan(1, 13, 1)  # Rule 4: 16
@@ -36,6 +44,8 @@ def test_planner():
     assert drt.plan(2 ** 20, 1024) == drt.Plan(1, 6, 1)  # Rule 4 as is below 2^24
     p = drt.plan(2 ** 30, 131072)
     assert p.mode == 1 and p.beta == 2 and p.alpha == 10  # beta = 2 shifts Rule 4's alpha by 2
+    assert drt.plan(2 ** 22, 2 ** 14) == drt.Plan(1, 5, 1)  # large k, n < 2^25: beta = 1, Rule 4
+    assert drt.plan(2 ** 25, 2 ** 14).beta == 2
     # small inputs and large k/n fall back to a plain radix select
     assert drt.plan(4096, 7).mode == 3  # one workgroup (n <= 2^16, k <= 2048)
     assert drt.plan(1 << 16, 2048).mode == 3 and drt.plan((1 << 16) + 1, 2048).mode == 1
