@@ -357,9 +357,9 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
 // delegate_wave); the caller checks that the chunk holds a multiple of
 // 4 * 64/G subranges.
 template <int DT, int BETA, bool VEC>
-__device__ __forceinline__ void delegate_grouped(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
-                                                 uint64_t clo, uint32_t wave, uint64_t chunk, bool fast,
-                                                 uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+__device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                                uint64_t clo, uint32_t wave, uint64_t chunk, uint32_t* dkey,
+                                                uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint32_t L = 1u << alpha;
   const uint32_t G = L / 64 > 8 ? L / 64 : 8;
@@ -370,34 +370,59 @@ __device__ __forceinline__ void delegate_grouped(const uint32_t* __restrict__ ke
   for (uint64_t bi = wave; bi < nbatch; bi += 4) {
     const uint64_t s = (clo >> alpha) + bi * ns + g;
     const uint64_t sbase = s << alpha;
-    const bool mine = sbase < n;
     TopB<BETA> tb;
     tb.clear();
     for (uint32_t i0 = 0; i0 < lpl; i0 += kUnroll) {
       uint32_t v[kUnroll][4];
-      if (fast) {
+      const uint64_t p0 = sbase + ((uint64_t)i0 * G + l) * 4;
+      if constexpr (BETA == 2) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, sbase + ((uint64_t)(i0 + u) * G + l) * 4, v[u]);
+        for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, p0 + (uint64_t)u * G * 4, v[u]);
+        // The lane's elements come in increasing position, so a later key
+        // equal to a held one ranks below it: the top two of this step's 32
+        // keys follow from 32-bit key compares alone, with positions kept as
+        // element numbers e (position p0 + (e / 4) * 4G + e % 4), and are
+        // folded into the running pair once per step.
+        uint32_t a0, a1, r0, r1;
+        {
+          const uint32_t x0 = enc<DT>(v[0][0]), x1 = enc<DT>(v[0][1]);
+          const bool sw = x1 > x0;
+          a0 = sw ? x1 : x0;
+          r0 = sw ? 1u : 0u;
+          a1 = sw ? x0 : x1;
+          r1 = sw ? 0u : 1u;
+        }
+#pragma unroll
+        for (int e = 2; e < kUnroll * 4; ++e) {
+          const uint32_t x = enc<DT>(v[e >> 2][e & 3]);
+          const bool g0 = x > a0, g1 = x > a1;
+          r1 = g1 ? (g0 ? r0 : (uint32_t)e) : r1;
+          r0 = g0 ? (uint32_t)e : r0;
+          // second = median of (a0, a1, x) (one v_med3_u32), first = max
+          const uint32_t mn = a0 < a1 ? a0 : a1, mx = a0 > a1 ? a0 : a1;
+          const uint32_t hi = mx < x ? mx : x;
+          a1 = mn > hi ? mn : hi;
+          a0 = a0 > x ? a0 : x;  // a0 >= a1 always
+        }
+        const uint32_t b0 = (uint32_t)p0, st = 4 * G;
+        tb.push(comp(a0, b0 + (r0 >> 2) * st + (r0 & 3)));
+        tb.push(comp(a1, b0 + (r1 >> 2) * st + (r1 & 3)));
       } else {
 #pragma unroll
+        for (int u = 0; u < kUnroll; ++u) load4<DT, VEC>(keys, p0 + (uint64_t)u * G * 4, v[u]);
+#pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const uint64_t p = sbase + ((uint64_t)(i0 + u) * G + l) * 4;
+          const uint32_t pu = (uint32_t)p0 + (uint32_t)u * G * 4;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) v[u][c] = (mine && p + c < n) ? keys[p + c] : 0u;
+          for (int c = 0; c < 4; ++c) tb.push(comp(enc<DT>(v[u][c]), pu + c));
         }
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const uint64_t p = sbase + ((uint64_t)(i0 + u) * G + l) * 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (fast || (mine && p + c < n)) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
       }
     }
     for (uint32_t m = 1; m < G; m <<= 1) tb.merge_xor((int)m);
-    if (l == 0 && mine) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
+    if (l == 0) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
   }
 }
+
 
 // Subranges of 4..128 elements: 2^(alpha-2) lanes per subrange inside each
 // 256-element wave-load; segmented butterfly merge.
@@ -460,8 +485,13 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   const bool grouped = BETA >= 2 && gspan && wlen % gspan == 0;
   if (alpha >= 8) {
     if (clo < n) {
-      if (grouped) delegate_grouped<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, clo + chunk <= n, dkey, didx, lh, &s_bmax);
-      else delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
+      // full chunks only: a bounds-checked copy of the unrolled grouped loop
+      // would set the register budget of the whole kernel (184 VGPRs against
+      // 60: 2 waves per SIMD instead of 8); the last chunk takes delegate_wave
+      if (grouped && clo + chunk <= n)
+        grouped_batches<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, dkey, didx, lh, &s_bmax);
+      else
+        delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
     }
   } else if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
