@@ -4,7 +4,7 @@ The paper evaluates unsigned 32-bit integers (Section 6) and states the
 problem for "largest" (Section 1).  For float32 it is silent; this project's
 reading is IEEE 754 totalOrder (negative NaNs lowest, then -inf ... -0, +0
 ... +inf, then positive NaNs), so every bit pattern has a place and -0 sorts
-below +0.
+below +0.  Signed 32-bit integers take their ordinary order.
 
 ``rank_key`` maps values to int64 numbers whose ordinary integer order is the
 ranking order.  For float32 it works on the signed 32-bit view of the bits:
@@ -33,6 +33,10 @@ def rank_key(values: np.ndarray, dtype: str) -> np.ndarray:
         s = v.view(np.int32).astype(np.int64)
         mag = s & 0x7FFFFFFF
         return np.where(s >= 0, s, -1 - mag)
+    if dtype == "i32":
+        if v.dtype != np.int32:
+            raise TypeError(f"i32 keys must be an int32 array, got {v.dtype}")
+        return v.astype(np.int64)
     raise ValueError(f"unknown dtype {dtype!r}")
 
 

@@ -3,12 +3,17 @@
 Problem statement (Section 1): top-k returns the k largest elements of V,
 k-selection the k-th largest.  This project fixes what the paper leaves open:
 
-* order: ``rank_key`` (uint32 as is; float32 by IEEE totalOrder);
+* order: ``rank_key`` (uint32 and int32 as is; float32 by IEEE totalOrder);
 * ties: among equal keys the lower position ranks first, so position i
   precedes j iff key[i] > key[j] or (key[i] == key[j] and i < j);
 * output: the k first positions in that order, i.e. values sorted by key
   descending with ties in ascending position; the k-th value counts
   multiplicity (the value at output slot k-1).
+
+``largest=False`` asks for the k smallest instead (the nearest-neighbour and
+least-score uses of the real-world datasets, Section 6): the same definition
+with the key order reversed and the same tie rule, i.e. i precedes j iff
+key[i] < key[j] or (key[i] == key[j] and i < j); values come out ascending.
 
 Every function returns ``(values, indices)`` with ``values`` the input's own
 bit patterns at ``indices``.
@@ -22,6 +27,13 @@ import numpy as np
 from .order import rank_key
 
 
+def _key(values: np.ndarray, dtype: str, largest: bool) -> np.ndarray:
+    """Ranking key: a larger number ranks first (for the k smallest, the
+    negated order key)."""
+    key = rank_key(values, dtype)
+    return key if largest else -key
+
+
 def _check(values: np.ndarray, k: int) -> int:
     n = int(np.asarray(values).shape[0])
     if not (1 <= k <= n):
@@ -29,14 +41,14 @@ def _check(values: np.ndarray, k: int) -> int:
     return n
 
 
-def topk_bruteforce(values: np.ndarray, k: int, dtype: str):
+def topk_bruteforce(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """O(n^2) ranks straight from the definition (pure Python; n <= a few thousand).
 
     rank(i) = #{j : key[j] > key[i]} + #{j < i : key[j] == key[i]}; the output
     slot r holds the unique i with rank(i) == r.
     """
     n = _check(values, k)
-    key = [int(x) for x in rank_key(values, dtype)]
+    key = [int(x) for x in _key(values, dtype, largest)]
     out = [None] * n
     for i in range(n):
         r = 0
@@ -48,16 +60,16 @@ def topk_bruteforce(values: np.ndarray, k: int, dtype: str):
     return np.asarray(values)[idx], idx
 
 
-def topk_sort(values: np.ndarray, k: int, dtype: str):
+def topk_sort(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """Sort-and-choose (Section 2.2): sort every position by (key desc, index asc), keep k."""
     n = _check(values, k)
-    key = rank_key(values, dtype)
+    key = _key(values, dtype, largest)
     order = np.lexsort((np.arange(n, dtype=np.int64), -key))
     idx = order[:k].astype(np.int64)
     return np.asarray(values)[idx], idx
 
 
-def topk_select(values: np.ndarray, k: int, dtype: str):
+def topk_select(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """k-selection first, then extraction (the selection route the paper's
     top-k algorithms follow, Section 2.2):
 
@@ -68,7 +80,7 @@ def topk_select(values: np.ndarray, k: int, dtype: str):
     4. order those k by (key desc, index asc).
     """
     n = _check(values, k)
-    key = rank_key(values, dtype)
+    key = _key(values, dtype, largest)
     T = np.partition(key, n - k)[n - k]
     above = np.flatnonzero(key > T)
     g = above.shape[0]
@@ -79,7 +91,7 @@ def topk_select(values: np.ndarray, k: int, dtype: str):
     return np.asarray(values)[idx], idx
 
 
-def topk_heap(values: np.ndarray, k: int, dtype: str):
+def topk_heap(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """The textbook priority-queue top-k (Section 1): a size-k min-heap slides
     over V; an element replaces the heap minimum when it ranks higher.
 
@@ -87,7 +99,7 @@ def topk_heap(values: np.ndarray, k: int, dtype: str):
     element (smallest key; among equal keys, the largest index).  Pure Python.
     """
     n = _check(values, k)
-    key = [int(x) for x in rank_key(values, dtype)]
+    key = [int(x) for x in _key(values, dtype, largest)]
     heap = []
     for i in range(n):
         item = (key[i], -i)
@@ -100,15 +112,16 @@ def topk_heap(values: np.ndarray, k: int, dtype: str):
     return np.asarray(values)[idx], idx
 
 
-def topk(values: np.ndarray, k: int, dtype: str):
+def topk(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """Reference answer at any size: the selection route (fast, numpy)."""
-    return topk_select(values, k, dtype)
+    return topk_select(values, k, dtype, largest)
 
 
-def kth_value(values: np.ndarray, k: int, dtype: str):
-    """k-selection (Section 1): the k-th largest value, counting multiplicity."""
+def kth_value(values: np.ndarray, k: int, dtype: str, largest: bool = True):
+    """k-selection (Section 1): the k-th largest value (or k-th smallest),
+    counting multiplicity."""
     n = _check(values, k)
-    key = rank_key(values, dtype)
+    key = _key(values, dtype, largest)
     T = np.partition(key, n - k)[n - k]
     i = int(np.flatnonzero(key == T)[0])
     return np.asarray(values)[i]

@@ -6,6 +6,7 @@ answer uniquely (so passing them is exact agreement too):
   I1 k outputs, distinct positions in range;
   I2 out_vals[r] is bit-identical to keys[out_idx[r]];
   I3 outputs strictly ordered by (key desc, position asc);
+(largest=False: the k smallest, every "desc" / "above" read in reverse order).
   I4 fewer than k keys rank strictly above the k-th, at least k at or above;
   I5 the k-th value appears k - #{key > kth} times in the output;
   I6 those tied outputs are the lowest positions holding the k-th value.
@@ -21,8 +22,9 @@ def to_np(t) -> np.ndarray:
     return t.detach().cpu().numpy()
 
 
-def check_exact(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_idx: np.ndarray, tag=""):
-    want_vals, want_idx = oracle.topk_reference(keys, k, dtype)
+def check_exact(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_idx: np.ndarray, tag="",
+                largest: bool = True):
+    want_vals, want_idx = oracle.topk_reference(keys, k, dtype, largest)
     gi = np.asarray(got_idx).view(np.uint32).astype(np.int64)
     assert gi.shape == (k,), (tag, gi.shape)
     bad = np.flatnonzero(gi != want_idx)
@@ -32,7 +34,9 @@ def check_exact(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_
     assert (gv == wv).all(), f"{tag}: values differ"
 
 
-def check_invariants(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_idx: np.ndarray, tag=""):
+def check_invariants(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_idx: np.ndarray, tag="",
+                     largest: bool = True):
+    sign = 1 if largest else -1
     n = keys.shape[0]
     gi = np.asarray(got_idx).view(np.uint32).astype(np.int64)
     gv = np.asarray(got_vals).view(np.uint32)
@@ -41,11 +45,11 @@ def check_invariants(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray,
     assert np.unique(gi).shape[0] == k, f"{tag}: repeated positions"  # I1
     kb = keys.view(np.uint32)
     assert (kb[gi] == gv).all(), f"{tag}: values are not the keys at the positions"  # I2
-    rk = oracle.rank_key(keys[gi], dtype)
+    rk = sign * oracle.rank_key(keys[gi], dtype)
     ok = (rk[:-1] > rk[1:]) | ((rk[:-1] == rk[1:]) & (gi[:-1] < gi[1:]))
     assert ok.all(), f"{tag}: outputs not in (key desc, position asc) order"  # I3
     kth = rk[-1]
-    full = oracle.rank_key(keys, dtype)
+    full = sign * oracle.rank_key(keys, dtype)
     greater = int(np.count_nonzero(full > kth))
     at_least = greater + int(np.count_nonzero(full == kth))
     assert greater < k <= at_least, f"{tag}: k-th value wrong ({greater}, {k}, {at_least})"  # I4

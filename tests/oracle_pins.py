@@ -184,3 +184,79 @@ def pin_paper_example(stages_mod) -> None:
         assert vals.tolist() == c["topk_values"], c["name"]
     a = g["alpha_rule_instance"]
     assert stages_mod.alpha_rule(2 ** a["log2_n"], 2 ** a["log2_k"], a["const"]) == a["alpha"]
+
+
+I32_ALPHABET = np.array([-2 ** 31, -1, 0, 1, 2 ** 31 - 1], dtype=np.int32)
+
+
+def pin_smallest_and_i32(topk_fn, seed: int = 13) -> None:
+    """The k smallest (largest=False) and signed int32 keys, against Python's
+    own sort, numpy's argmin / stable argsort / sort, and hand-ordered lists."""
+    rng = np.random.default_rng(seed)
+    # exhaustive tiny arrays, k smallest: Python's sort on (key asc, position asc)
+    for n in range(1, 5):
+        for combo in itertools.product(range(len(ALPHABET)), repeat=n):
+            v = ALPHABET[list(combo)]
+            want = sorted(range(n), key=lambda i: (int(v[i]), i))
+            for k in range(1, n + 1):
+                vals, idx = topk_fn(v, k, "u32", largest=False)
+                assert list(map(int, idx)) == want[:k], (v.tolist(), k, list(idx), want[:k])
+                assert (np.asarray(vals).view(np.uint32) == v[want[:k]]).all()
+    # exhaustive tiny int32 arrays over {-2^31, -1, 0, 1, 2^31-1}, both orders
+    for n in range(1, 4):
+        for combo in itertools.product(range(len(I32_ALPHABET)), repeat=n):
+            v = I32_ALPHABET[list(combo)]
+            up = sorted(range(n), key=lambda i: (int(v[i]), i))
+            down = sorted(range(n), key=lambda i: (-int(v[i]), i))
+            for k in range(1, n + 1):
+                assert list(map(int, topk_fn(v, k, "i32", largest=False)[1])) == up[:k]
+                assert list(map(int, topk_fn(v, k, "i32")[1])) == down[:k], (v.tolist(), k)
+    # k = 1 smallest: numpy argmin (first position of the minimum)
+    for n in (1, 2, 17, 1000):
+        v = rng.integers(0, 50, size=n, dtype=np.uint32)
+        assert int(topk_fn(v, 1, "u32", largest=False)[1][0]) == int(np.argmin(v))
+        w = rng.integers(-25, 25, size=n).astype(np.int32)
+        assert int(topk_fn(w, 1, "i32", largest=False)[1][0]) == int(np.argmin(w))
+        assert int(topk_fn(w, 1, "i32")[1][0]) == int(np.argmax(w))
+    # k = n: numpy's stable ascending argsort (and descending via the negation)
+    for n in (1, 5, 300):
+        v = rng.integers(0, 20, size=n, dtype=np.uint32)
+        assert (np.asarray(topk_fn(v, n, "u32", largest=False)[1]) == np.argsort(v, kind="stable")).all()
+        w = rng.integers(-10, 10, size=n).astype(np.int32)
+        assert (np.asarray(topk_fn(w, n, "i32", largest=False)[1]) == np.argsort(w, kind="stable")).all()
+        assert (np.asarray(topk_fn(w, n, "i32")[1]) ==
+                np.argsort(-w.astype(np.int64), kind="stable")).all()
+        # float32 without NaNs and without -0: numpy's value order is totalOrder there
+        f = (rng.integers(-8, 8, size=n) * 0.5 + 0.25).astype(np.float32)
+        assert (np.asarray(topk_fn(f, n, "f32", largest=False)[1]) == np.argsort(f, kind="stable")).all()
+    # float32 totalOrder upwards: a hand-ordered chain, shuffled
+    chain = f32_chain().view(np.float32)
+    perm = rng.permutation(chain.shape[0])
+    _, idx = topk_fn(chain[perm], chain.shape[0], "f32", largest=False)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.shape[0])
+    assert list(map(int, idx)) == [int(inv[j]) for j in range(chain.shape[0])]
+    # heavy duplicates upwards, each value in position order
+    v = rng.integers(0, 6, size=400, dtype=np.uint32)
+    for k in (1, 30, 250, 400):
+        want = []
+        for val in sorted(set(v.tolist())):
+            want.extend(np.flatnonzero(v == val).tolist())
+        assert list(map(int, topk_fn(v, k, "u32", largest=False)[1])) == want[:k]
+    # value multisets against numpy's sort
+    v = rng.integers(0, 2 ** 32, size=5000, dtype=np.uint32)
+    assert (np.asarray(topk_fn(v, 777, "u32", largest=False)[0]) == np.sort(v)[:777]).all()
+    w = rng.integers(-2 ** 31, 2 ** 31, size=5000).astype(np.int32)
+    assert (np.asarray(topk_fn(w, 777, "i32")[0]) == np.sort(w)[::-1][:777]).all()
+
+
+def pin_kth_smallest(kth_fn, seed: int = 17) -> None:
+    """k-th smallest (counting multiplicity) = numpy's ascending sort at k-1."""
+    rng = np.random.default_rng(seed)
+    for n in (1, 9, 1000):
+        v = rng.integers(0, 30, size=n, dtype=np.uint32)
+        w = rng.integers(-15, 15, size=n).astype(np.int32)
+        for k in sorted({1, n, max(1, n // 3)}):
+            assert int(kth_fn(v, k, "u32", largest=False)) == int(np.sort(v)[k - 1])
+            assert int(kth_fn(w, k, "i32", largest=False)) == int(np.sort(w)[k - 1])
+            assert int(kth_fn(w, k, "i32")) == int(np.sort(w)[::-1][k - 1])

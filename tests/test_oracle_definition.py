@@ -29,22 +29,35 @@ def test_kth():
     pins.pin_kth(oracle.kth_value)
 
 
-@pytest.mark.parametrize("dtype", ["u32", "f32"])
-def test_routes_agree_random(dtype):
+@pytest.mark.parametrize("fn", ROUTES + [oracle.topk_bruteforce], ids=lambda f: f.__name__)
+def test_smallest_and_i32(fn):
+    pins.pin_smallest_and_i32(fn)
+
+
+def test_kth_smallest():
+    pins.pin_kth_smallest(oracle.kth_value)
+
+
+@pytest.mark.parametrize("largest", [True, False])
+@pytest.mark.parametrize("dtype", ["u32", "f32", "i32"])
+def test_routes_agree_random(dtype, largest):
     rng = np.random.default_rng(1)
     for n in (1, 2, 63, 64, 65, 1000, 4097):
         if dtype == "u32":
             v = rng.integers(0, 2 ** 32, size=n, dtype=np.uint32)
             v[rng.integers(0, n, size=n // 4)] = v[0]  # plant ties
+        elif dtype == "i32":
+            v = rng.integers(-2 ** 31, 2 ** 31, size=n).astype(np.int32)
+            v[rng.integers(0, n, size=n // 4)] = v[0]
         else:
             v = rng.standard_normal(n).astype(np.float32)
             v[rng.integers(0, n, size=n // 4)] = v[0]
         for k in sorted({1, n, max(1, n // 2), min(n, 17)}):
-            a = oracle.topk_sort(v, k, dtype)[1]
-            b = oracle.topk_select(v, k, dtype)[1]
+            a = oracle.topk_sort(v, k, dtype, largest)[1]
+            b = oracle.topk_select(v, k, dtype, largest)[1]
             assert (a == b).all()
             if n <= 1000:
-                c = oracle.topk_heap(v, k, dtype)[1]
+                c = oracle.topk_heap(v, k, dtype, largest)[1]
                 assert (a == c).all()
 
 

@@ -61,6 +61,24 @@ def _heap_wrong_tiebreak(values, k, dtype):
     return values[idx], idx
 
 
+def _smallest_ties_desc(values, k, dtype, largest=True):
+    # mistake: for the k smallest, ties in descending position (negating the
+    # whole (key, position) order instead of the key alone)
+    n = values.shape[0]
+    key = order.rank_key(values, dtype)
+    o = np.lexsort((np.arange(n), -key))[::-1][:k] if not largest else np.lexsort((np.arange(n), -key))[:k]
+    return values[o], o
+
+
+def _i32_unsigned(values, k, dtype, largest=True):
+    # mistake: int32 ranked by its unsigned bit pattern
+    v = np.asarray(values)
+    key = v.view(np.uint32).astype(np.int64) if dtype == "i32" else order.rank_key(v, dtype)
+    key = key if largest else -key
+    o = np.lexsort((np.arange(v.shape[0]), -key))[:k]
+    return v[o], o
+
+
 def _with_key(fn_key):
     def f(values, k, dtype):
         n = values.shape[0]
@@ -76,6 +94,8 @@ MUTANTS = {
     "ties_descending": (_sort_ties_desc, pins.pin_closed_forms_u32),
     "select_off_by_one": (_select_off_by_one, pins.pin_exhaustive_u32),
     "heap_tiebreak": (_heap_wrong_tiebreak, pins.pin_exhaustive_u32),
+    "smallest_ties_descending": (_smallest_ties_desc, pins.pin_smallest_and_i32),
+    "i32_unsigned_order": (_i32_unsigned, pins.pin_smallest_and_i32),
 }
 
 
