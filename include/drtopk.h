@@ -9,8 +9,9 @@
  * skip every subrange that cannot reach it, and select among the survivors.
  *
  * Conventions fixed by this library where the paper is silent:
- *   - keys are uint32 (as the paper evaluates) or float32, the latter ordered
- *     by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN);
+ *   - keys are uint32 (as the paper evaluates), int32, or float32, the latter
+ *     ordered by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf
+ *     < +NaN); DRTOPK_SMALLEST asks for the k smallest instead;
  *   - among equal keys the lower position ranks first, so the answer is unique:
  *     out_vals is sorted by key descending, ties by ascending position, and
  *     out_vals[k-1] is the k-th largest counting multiplicity;
@@ -39,7 +40,11 @@
 extern "C" {
 #endif
 
-typedef enum { DRTOPK_U32 = 0, DRTOPK_F32 = 1 } drtopk_dtype_t;
+/* Key types.  DRTOPK_SMALLEST may be OR-ed into any dtype argument or field:
+ * the call then works on the k smallest keys (the paper's nearest-neighbour
+ * and least-score uses, Section 6) -- out_vals ascending, ties by ascending
+ * position, the k-th value the k-th smallest.  Everything else is the same. */
+typedef enum { DRTOPK_U32 = 0, DRTOPK_F32 = 1, DRTOPK_I32 = 2, DRTOPK_SMALLEST = 0x100 } drtopk_dtype_t;
 
 typedef enum {
   DRTOPK_OK = 0,

@@ -20,7 +20,9 @@ LIB_PATH = os.path.join(HERE, "libdrtopk.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "drtopk.h")
 TUNING_PATH = os.path.join(HERE, "tuning.json")  # written by paper_2109_08219_amd.tune
 
-U32, F32 = 0, 1
+U32, F32, I32 = 0, 1, 2
+SMALLEST = 0x100  # OR-ed into a dtype code: the k smallest instead of the k largest
+_DTYPES = {"u32": U32, "f32": F32, "i32": I32}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported"}
 
 
@@ -138,21 +140,23 @@ def _torch():
 def _dtype_code(t, dtype):
     torch = _torch()
     if dtype is not None:
-        return {"u32": U32, "f32": F32}[dtype]
+        return _DTYPES[dtype]
     if t.dtype == torch.float32:
         return F32
     if t.dtype == torch.uint32:
         return U32
-    raise TypeError(f"keys must be torch.uint32 or torch.float32 (got {t.dtype}); "
+    if t.dtype == torch.int32:
+        return I32
+    raise TypeError(f"keys must be torch.uint32, torch.int32 or torch.float32 (got {t.dtype}); "
                     "pass dtype='u32' to read other 4-byte data as uint32")
 
 
-def _prep(keys, dtype):
+def _prep(keys, dtype, largest: bool = True):
     if not keys.is_cuda:
         raise ValueError("keys must be a GPU tensor")
     if keys.dim() != 1 or not keys.is_contiguous() or keys.element_size() != 4:
         raise ValueError("keys must be a contiguous 1-D tensor of 4-byte elements")
-    return _dtype_code(keys, dtype)
+    return _dtype_code(keys, dtype) | (0 if largest else SMALLEST)
 
 
 def _stream(stream):
@@ -168,14 +172,15 @@ def _opts(alpha, beta, mode, variant=0):
                    variant)
 
 
-def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, alpha=None, beta=None,
-                mode=None, variant: int = 0, stats: bool = False, stream=None):
-    """The k largest keys, sorted descending (ties: lower position first), and their positions.
+def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, largest: bool = True, alpha=None,
+                beta=None, mode=None, variant: int = 0, stats: bool = False, stream=None):
+    """The k largest keys, sorted descending (ties: lower position first), and their positions;
+    largest=False: the k smallest, sorted ascending (ties: lower position first).
 
     Returns (values, indices[, Stats]).  values has the keys' dtype; indices are int64-free uint32
     positions stored in a torch.int32 tensor (bit pattern of the uint32 position)."""
     torch = _torch()
-    code = _prep(keys, dtype)
+    code = _prep(keys, dtype, largest)
     if out_vals is None:
         out_vals = torch.empty(k, dtype=keys.dtype, device=keys.device)
     if out_idx is None:
@@ -192,10 +197,10 @@ def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, alpha=
     return (out_vals, out_idx, st) if stats else (out_vals, out_idx)
 
 
-def kth_select(keys, k: int, out=None, *, dtype=None, stream=None):
-    """The k-th largest key (counting multiplicity) as a 1-element tensor."""
+def kth_select(keys, k: int, out=None, *, dtype=None, largest: bool = True, stream=None):
+    """The k-th largest key (largest=False: k-th smallest), counting multiplicity, as a 1-element tensor."""
     torch = _torch()
-    code = _prep(keys, dtype)
+    code = _prep(keys, dtype, largest)
     if out is None:
         out = torch.empty(1, dtype=keys.dtype, device=keys.device)
     rc = lib().kth_select(ctypes.c_void_p(keys.data_ptr()), keys.numel(), k, code,
@@ -207,7 +212,8 @@ def kth_select(keys, k: int, out=None, *, dtype=None, stream=None):
 class Batch:
     """A fixed set of top-k problems with packed device outputs, reusable across calls.
 
-    problems: list of (keys, k) or (keys, k, dtype).  All outputs of problem i live in
+    problems: list of (keys, k), (keys, k, dtype) or (keys, k, dtype, largest) -- dtype None
+    = from the tensor, largest False = the k smallest.  All outputs of problem i live in
     three packed int32 buffers: vals[off[i] : off[i] + k_i] (bit patterns of the keys'
     dtype), idx[same range] (uint32 positions) and kth[i].  kth_only=True asks for the
     k-th values alone (no vals / idx buffers).  The descriptors are built once; run()
@@ -219,7 +225,8 @@ class Batch:
         self.count = len(problems)
         self.keys = [pr[0] for pr in problems]
         self.ks = [int(pr[1]) for pr in problems]
-        self.codes = [_prep(pr[0], pr[2] if len(pr) > 2 else None) for pr in problems]
+        self.codes = [_prep(pr[0], pr[2] if len(pr) > 2 else None, pr[3] if len(pr) > 3 else True)
+                      for pr in problems]
         self.kth_only = kth_only
         dev = self.keys[0].device if self.keys else torch.device("cuda")
         self.off = [0] * self.count
@@ -262,7 +269,7 @@ class Batch:
 
 
 def topk_select_batched(problems, *, stream=None):
-    """problems: list of (keys, k) or (keys, k, dtype).  Returns a list of (values, indices, kth)."""
+    """problems as for Batch.  Returns a list of (values, indices, kth)."""
     b = Batch(problems)
     b.run(stream)
     return [(b.values(i), b.indices(i), b.kth_value(i)) for i in range(b.count)]
@@ -313,9 +320,17 @@ class Plan:
     beta: int
 
 
+def _dtype_arg(dtype) -> int:
+    """'u32' / 'f32' / 'i32', optionally with a '-min' suffix (the k smallest), or a code."""
+    if isinstance(dtype, int):
+        return dtype
+    base, _, order = dtype.partition("-")
+    return _DTYPES[base] | (SMALLEST if order == "min" else 0)
+
+
 def plan(n: int, k: int, dtype: str = "u32") -> Plan:
     o = Options()
-    _check(lib().drtopk_plan(n, k, {"u32": U32, "f32": F32}[dtype], ctypes.byref(o)), "drtopk_plan")
+    _check(lib().drtopk_plan(n, k, _dtype_arg(dtype), ctypes.byref(o)), "drtopk_plan")
     return Plan(o.mode, o.alpha, o.beta)
 
 
@@ -358,7 +373,7 @@ def batched_route(n: int, k: int) -> tuple[int, int]:
 def footprint(n: int, k: int, dtype: str = "u32") -> int:
     """HBM bytes a problem occupies while in flight (input, outputs, workspace)."""
     b = ctypes.c_uint64()
-    _check(lib().drtopk_footprint(n, k, {"u32": U32, "f32": F32}[dtype], ctypes.byref(b)), "drtopk_footprint")
+    _check(lib().drtopk_footprint(n, k, _dtype_arg(dtype), ctypes.byref(b)), "drtopk_footprint")
     return b.value
 
 

@@ -139,12 +139,42 @@ __device__ inline void bb_bucket(const uint32_t* h, uint32_t rank, BatchSmem& sm
   __syncthreads();
 }
 
+// Key codec of a batched problem, applied at run time so one kernel serves
+// batches that mix key types and orders: enc(b) = b ^ (sign(b) & a) ^ c
+// equals enc<DT> of the problem's codec (float32: a = 0x7FFFFFFF, c = the
+// sign bit; int32: a = 0, c = the sign bit; uint32: both 0; the k smallest:
+// c complemented).  a leaves bit 31 alone, so b ^ (sign(b) & a) keeps b's
+// sign and dec recovers b from it.
+struct Codec {
+  uint32_t a, c;
+  __device__ __forceinline__ uint32_t enc(uint32_t b) const {
+    return b ^ ((uint32_t)((int32_t)b >> 31) & a) ^ c;
+  }
+  __device__ __forceinline__ uint32_t dec(uint32_t e) const {
+    const uint32_t v = e ^ c;
+    return v ^ ((uint32_t)((int32_t)v >> 31) & a);
+  }
+};
+__device__ __forceinline__ Codec codec_of(uint32_t code) {
+  Codec x;
+  x.a = (code & 3u) == (uint32_t)DT_F32 ? 0x7FFFFFFFu : 0u;
+  x.c = ((code & 3u) == (uint32_t)DT_U32 ? 0u : 0x80000000u) ^ ((code & (uint32_t)DT_MIN) ? 0xFFFFFFFFu : 0u);
+  return x;
+}
+__device__ __forceinline__ void b_write_out(uint64_t c, uint32_t r, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
+                                            uint32_t* out_kth, Codec cx) {
+  const uint32_t v = cx.dec(comp_key(c));
+  if (out_vals) out_vals[r] = v;
+  if (out_idx) out_idx[r] = comp_pos(c);
+  if (out_kth && r == k - 1) *out_kth = v;
+}
+
 // Sorts `cnt` composites from LDS array `src` and writes the first `k` as
 // outputs 0..k-1.  `src` holds at least E * kBT entries and serves as the
 // exchange buffer of the sort once every thread has loaded its elements.
-template <int DT, int E>
+template <int E>
 __device__ __noinline__ void b_sort_write_e(uint64_t* src, uint32_t cnt, uint32_t k, uint32_t* out_vals,
-                                            uint32_t* out_idx, uint32_t* out_kth) {
+                                            uint32_t* out_idx, uint32_t* out_kth, Codec cx) {
   uint64_t v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -155,18 +185,17 @@ __device__ __noinline__ void b_sort_write_e(uint64_t* src, uint32_t cnt, uint32_
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const uint32_t g = threadIdx.x * E + e;
-    if (g < k) write_out<DT>(v[e], g, k, out_vals, out_idx, out_kth);
+    if (g < k) b_write_out(v[e], g, k, out_vals, out_idx, out_kth, cx);
   }
 }
 
 // cnt <= kBT * 8, k <= cnt.
-template <int DT>
 __device__ inline void b_sort_write(uint64_t* src, uint32_t cnt, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
-                                    uint32_t* out_kth) {
-  if (cnt <= 1u * kBT) b_sort_write_e<DT, 1>(src, cnt, k, out_vals, out_idx, out_kth);
-  else if (cnt <= 2u * kBT) b_sort_write_e<DT, 2>(src, cnt, k, out_vals, out_idx, out_kth);
-  else if (cnt <= 4u * kBT) b_sort_write_e<DT, 4>(src, cnt, k, out_vals, out_idx, out_kth);
-  else b_sort_write_e<DT, 8>(src, cnt, k, out_vals, out_idx, out_kth);
+                                    uint32_t* out_kth, Codec cx) {
+  if (cnt <= 1u * kBT) b_sort_write_e<1>(src, cnt, k, out_vals, out_idx, out_kth, cx);
+  else if (cnt <= 2u * kBT) b_sort_write_e<2>(src, cnt, k, out_vals, out_idx, out_kth, cx);
+  else if (cnt <= 4u * kBT) b_sort_write_e<4>(src, cnt, k, out_vals, out_idx, out_kth, cx);
+  else b_sort_write_e<8>(src, cnt, k, out_vals, out_idx, out_kth, cx);
 }
 
 // The rank-th largest (1-based) of the distinct composites a[0..cnt) in LDS:
@@ -203,8 +232,9 @@ __device__ inline uint64_t lds_select(const uint64_t* a, uint32_t cnt, uint32_t 
 
 // Problems of at most kBSmallN keys: composites into LDS, the k-th by radix
 // select, the k at or above it compacted and sorted.
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
+  const Codec cx = codec_of(d.dtype);
   const uint32_t n = (uint32_t)d.n, k = d.k, n4 = vec_end<VEC>(n);
   const Keys<VEC> ks(d.keys, n4);
   for (uint32_t i = threadIdx.x * 4; i < n4; i += kBT * 4) {
@@ -212,10 +242,10 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
     ks.load4(i, v);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      if (i + c < n4) sm.surv[i + c] = comp(enc<DT>(v[c]), i + c);
+      if (i + c < n4) sm.surv[i + c] = comp(cx.enc(v[c]), i + c);
   }
   if (threadIdx.x == 0)
-    for (uint32_t i = n4; i < n; ++i) sm.surv[i] = comp(enc<DT>(d.keys[i]), i);
+    for (uint32_t i = n4; i < n; ++i) sm.surv[i] = comp(codec_of(d.dtype).enc(d.keys[i]), i);
   __syncthreads();
   uint32_t cnt = n;
   uint64_t* src = sm.surv;
@@ -231,7 +261,7 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
     cnt = k;
     src = sm.D;
   }
-  b_sort_write<DT>(src, cnt, k, d.out_vals, d.out_idx, d.out_kth);
+  b_sort_write(src, cnt, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
 }
 
 // Block-level MSD radix select over the problem's 64-bit composites: each
@@ -240,8 +270,9 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
 // soon as the elements ranked above the class plus the class itself fit the
 // LDS, they are compacted, sorted and the first k written: two passes over
 // the keys for typical inputs, at most seven for massive ties.
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
+  const Codec cx = codec_of(d.dtype);
   const uint32_t n = (uint32_t)d.n, k = d.k, n4 = vec_end<VEC>(n);
   const Keys<VEC> ks(d.keys, n4);
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
@@ -261,13 +292,13 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t i = base + j * 256 + lane * 4 + c;
-          const uint64_t x = comp(enc<DT>(v[j][c]), i);
+          const uint64_t x = comp(cx.enc(v[j][c]), i);
           if (i < n4 && (x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
         }
     }
     if (threadIdx.x == 0)
       for (uint32_t i = n4; i < n; ++i) {
-        const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+        const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
         if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
       }
     __syncthreads();
@@ -290,7 +321,7 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t i = base + j * 256 + lane * 4 + c;
-        const uint64_t x = comp(enc<DT>(v[j][c]), i);
+        const uint64_t x = comp(cx.enc(v[j][c]), i);
         if (i < n4 && (x & mask) >= prefix) {
           const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
           if (slot < kBSurv) sm.surv[slot] = x;
@@ -299,7 +330,7 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
   }
   if (threadIdx.x == 0)
     for (uint32_t i = n4; i < n; ++i) {
-      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
       if ((x & mask) >= prefix) {
         const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
         if (slot < kBSurv) sm.surv[slot] = x;
@@ -307,7 +338,7 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
     }
   __syncthreads();
   const uint32_t ns = sm.nsurv < kBSurv ? sm.nsurv : kBSurv;
-  b_sort_write<DT>(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth);
+  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
 }
 
 // Delegate vector for subranges of at least 256 keys, over the keys
@@ -316,9 +347,9 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
 // lies inside one subrange, whose delegate (sm.D[s - lo / 2^alpha]) takes the
 // block's maximum by an LDS atomic max (D starts at 0, below every composite
 // of a real element).
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4, uint32_t alpha,
-                                        BatchSmem& sm) {
+                                        Codec cx, BatchSmem& sm) {
   const uint32_t L = 1u << alpha;
   const uint32_t end = hi < n4 ? hi : n4;
   const uint32_t s0 = lo >> alpha;
@@ -334,7 +365,7 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
-          const uint64_t x = comp(enc<DT>(v[j][c]), p);
+          const uint64_t x = comp(cx.enc(v[j][c]), p);
           if (p < end && x > m) m = x;
         }
       m = wave_max64(m);
@@ -346,7 +377,7 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
-          const uint64_t x = comp(enc<DT>(v[j][c]), p);
+          const uint64_t x = comp(cx.enc(v[j][c]), p);
           if (p < end && x > m) m = x;
         }
         m = wave_max64(m);
@@ -359,13 +390,12 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32
 
 // The last n mod 4 keys (16-byte loads stop at n4), all in one subrange:
 // one thread folds them into its delegate sm.D[n4 / 2^alpha - s0].
-template <int DT>
 __device__ __forceinline__ void b_delegates_tail(const BatchDesc& d, uint32_t n4, uint32_t s0, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n;
   if (threadIdx.x == 0 && n4 < n) {
     uint64_t m = 0;
     for (uint32_t i = n4; i < n; ++i) {
-      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
       m = x > m ? x : m;
     }
     atomicMax((unsigned long long*)&sm.D[(n4 >> d.alpha) - s0], (unsigned long long)m);
@@ -375,8 +405,9 @@ __device__ __forceinline__ void b_delegates_tail(const BatchDesc& d, uint32_t n4
 // Delegate vector for subranges of 4..128 keys: each 256-key wave-load holds
 // whole subranges, 2^(alpha-2) lanes each; a segmented butterfly gives each
 // subrange's maximum to its first lane.
-template <int DT, bool VEC>
-__device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, BatchSmem& sm) {
+template <bool VEC>
+__device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, Codec cx,
+                                          BatchSmem& sm) {
   const uint32_t G = 1u << (alpha - 2);  // lanes per subrange
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
@@ -389,7 +420,7 @@ __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint
       uint64_t m = 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const uint64_t x = comp(enc<DT>(v[j][c]), p + c);
+        const uint64_t x = comp(cx.enc(v[j][c]), p + c);
         if (p + c < n4 && x > m) m = x;
       }
       for (uint32_t o = 1; o < G; o <<= 1) {
@@ -404,9 +435,9 @@ __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint
 // Survivors: every element ranked >= t in the k-1 subranges listed in Q,
 // read as one virtual vector of (k-1) * 2^alpha keys in 4-key pieces (a
 // piece never crosses a subrange).
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k, uint32_t alpha, const uint32_t* Q,
-                                   uint64_t t, BatchSmem& sm) {
+                                   uint64_t t, Codec cx, BatchSmem& sm) {
   const uint32_t L = 1u << alpha;
   const uint32_t total = (k - 1) << alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
@@ -424,7 +455,7 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint32_t p = pb[j] + c;
-        const uint64_t x = comp(enc<DT>(v[j][c]), p);
+        const uint64_t x = comp(cx.enc(v[j][c]), p);
         if (p < n4 && x >= t) {
           const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
           if (slot < kBSurv) sm.surv[slot] = x;
@@ -436,7 +467,7 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
 // Everything after the delegate vector (complete in sm.D[0..S)): t, the
 // qualifying subranges, the survivors and the output.  False if the survivors
 // overflow LDS (nothing has been written then).
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline bool b_finish(const BatchDesc& d, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
@@ -452,10 +483,10 @@ __device__ inline bool b_finish(const BatchDesc& d, BatchSmem& sm) {
     if (x > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(x) >> alpha;
   }
   __syncthreads();
-  b_survivors<DT, VEC>(ks, n4, k, alpha, Q, t, sm);
+  b_survivors<VEC>(ks, n4, k, alpha, Q, t, codec_of(d.dtype), sm);
   if (threadIdx.x == 0 && n4 < n && sm.tail_del > t) {  // the last keys, when their subrange is listed
     for (uint32_t i = n4; i < n; ++i) {
-      const uint64_t x = comp(enc<DT>(d.keys[i]), i);
+      const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
       if (x >= t) {
         const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
         if (slot < kBSurv) sm.surv[slot] = x;
@@ -465,24 +496,24 @@ __device__ inline bool b_finish(const BatchDesc& d, BatchSmem& sm) {
   __syncthreads();
   const uint32_t ns = sm.nsurv;
   if (ns > kBSurv) return false;
-  b_sort_write<DT>(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth);
+  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
   return true;
 }
 
 // The delegate method for one problem in one workgroup; false if the
 // survivors overflow LDS (nothing has been written then).
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
   const Keys<VEC> ks(d.keys, n4);
   for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
   __syncthreads();
-  if (alpha >= 8) b_delegates_wide<DT, VEC>(ks, 0, n, n4, alpha, sm);
-  else b_delegates_narrow<DT, VEC>(ks, n4, alpha, sm);
-  b_delegates_tail<DT>(d, n4, 0, sm);
+  if (alpha >= 8) b_delegates_wide<VEC>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
+  else b_delegates_narrow<VEC>(ks, n4, alpha, codec_of(d.dtype), sm);
+  b_delegates_tail(d, n4, 0, sm);
   __syncthreads();
-  return b_finish<DT, VEC>(d, sm);
+  return b_finish<VEC>(d, sm);
 }
 
 __device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
@@ -494,24 +525,24 @@ __device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
 // counts itself in; the workgroup that arrives last loads the whole delegate
 // vector and finishes the problem (radix select over the keys if its
 // survivors overflow).  Nobody waits for anybody.
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm);
 
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
   if (d.n <= kBSmallN) {
-    b_small<DT, VEC>(d, sm);
+    b_small<VEC>(d, sm);
     return;
   }
   if (d.alpha >= 2) {
     const uint64_t S = (d.n + (1ull << d.alpha) - 1) >> d.alpha;
-    if (S <= kBMaxS && S > d.k && b_delegate<DT, VEC>(d, sm)) return;
+    if (S <= kBMaxS && S > d.k && b_delegate<VEC>(d, sm)) return;
     __syncthreads();
   }
-  b_radix<DT, VEC>(d, sm);
+  b_radix<VEC>(d, sm);
 }
 
-template <int DT, bool VEC>
+template <bool VEC>
 __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t tlog = alpha > kBTileLog ? alpha : kBTileLog;
@@ -522,8 +553,8 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   const Keys<VEC> ks(d.keys, n4);
   for (uint32_t i = threadIdx.x; i < ns; i += kBT) sm.D[i] = 0;
   __syncthreads();
-  b_delegates_wide<DT, VEC>(ks, lo, hi, n4, alpha, sm);
-  if (hi == n) b_delegates_tail<DT>(d, n4, s0, sm);
+  b_delegates_wide<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
+  if (hi == n) b_delegates_tail(d, n4, s0, sm);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < ns; i += kBT) st_coh64(&Dg[d.doff + s0 + i], sm.D[i]);
   __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
@@ -534,31 +565,21 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
   for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
   __syncthreads();
-  if (b_finish<DT, VEC>(d, sm)) return;
+  if (b_finish<VEC>(d, sm)) return;
   __syncthreads();
-  b_radix<DT, VEC>(d, sm);
+  b_radix<VEC>(d, sm);
 }
 
 __device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (d.dtype == DT_F32) {
-    if (vec) b_problem_v<DT_F32, true>(d, sm);
-    else b_problem_v<DT_F32, false>(d, sm);
-  } else {
-    if (vec) b_problem_v<DT_U32, true>(d, sm);
-    else b_problem_v<DT_U32, false>(d, sm);
-  }
+  if (vec) b_problem_v<true>(d, sm);
+  else b_problem_v<false>(d, sm);
 }
 
 __device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (d.dtype == DT_F32) {
-    if (vec) b_tile<DT_F32, true>(d, tile, arrive, Dg, sm);
-    else b_tile<DT_F32, false>(d, tile, arrive, Dg, sm);
-  } else {
-    if (vec) b_tile<DT_U32, true>(d, tile, arrive, Dg, sm);
-    else b_tile<DT_U32, false>(d, tile, arrive, Dg, sm);
-  }
+  if (vec) b_tile<true>(d, tile, arrive, Dg, sm);
+  else b_tile<false>(d, tile, arrive, Dg, sm);
 }
 
 // Work items (problem << 8 | tile), claimed from *counter (starts at 0):

@@ -22,34 +22,21 @@
 #include <vector>
 
 #include "drtopk.h"
-#include "kernels.h"
-#include "tail.h"
+#include "host.h"
 #include "batched.h"
 
 namespace drtopk {
+
+thread_local hipError_t tl_launch_err = hipSuccess;
+Timing g_timing;
+
 namespace {
 
 constexpr double kAlphaConst = 3.0;  // Rule 4's const; the paper tuned it to 3
 
-struct Plan {
-  int mode = 0;  // 1 delegate method, 2 plain radix select on V, 3 one workgroup (batched kernel)
-  int alpha = 0, beta = 1;
-  int dt = 0;
-  uint64_t n = 0;
-  uint32_t k = 0;
-  uint64_t S = 0, nd = 0, cap_c = 0, chunk = 0, M = 0;
-  uint32_t kD = 0;   // rank sought among the delegates: min(k, |D|)
-  uint32_t slack = 0;
-  int variant = 0;   // 0: cooperative tail kernel, 1: one kernel per step
-  bool all = false;  // fewer real delegates than k: no threshold, every subrange qualifies
-  bool vec = false;
-  size_t off_ctl = 0, off_dkey = 0, off_didx = 0, off_q = 0, off_ckey = 0, off_cidx = 0;
-  size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, off_skey = 0, off_sidx = 0, total = 0;
-};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-thread_local hipError_t tl_launch_err = hipSuccess;  // launches whose API reports errors directly
 
 int rule_alpha(uint64_t n, uint32_t k) {
   const double a = 0.5 * (std::log2((double)n) - std::log2((double)k) + kAlphaConst);
@@ -289,286 +276,41 @@ int ensure_batch_bytes(Workspace* ws, size_t need, size_t dev_need) {
   return DRTOPK_OK;
 }
 
-template <typename T>
-T* at(void* base, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+
+
+
+
+
+
+// Public dtype (DRTOPK_U32 / F32 / I32, optionally | DRTOPK_SMALLEST) to the
+// kernels' codec.
+bool dtype_ok(int dtype) {
+  const int base = dtype & ~DRTOPK_SMALLEST;
+  return base == DRTOPK_U32 || base == DRTOPK_F32 || base == DRTOPK_I32;
 }
-
-unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap) {
-  uint64_t g = (items + per_block - 1) / per_block;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (unsigned)g;
-}
-
-// ---------------------------------------------------------------------------
-// optional phase timing (events on the call's own stream)
-struct Timing {
-  std::mutex mu;
-  bool on = false;
-  struct Rec { hipEvent_t a, b, c; };
-  std::vector<Rec> pending;
-  std::vector<hipEvent_t> pool;
-  hipEvent_t take() {
-    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-} g_timing;
-
-struct PhaseMarks {
-  hipEvent_t a = nullptr, b = nullptr, c = nullptr;
-  bool on = false;
-  void begin(hipStream_t st) {
-    std::lock_guard<std::mutex> g(g_timing.mu);
-    if (!g_timing.on) return;
-    a = g_timing.take(); b = g_timing.take(); c = g_timing.take();
-    on = a && b && c;
-    (void)st;
-  }
-  void start(hipStream_t st) { if (on) (void)hipEventRecord(a, st); }
-  void mid(hipStream_t st) { if (on) (void)hipEventRecord(b, st); }
-  void end(hipStream_t st) {
-    if (!on) return;
-    (void)hipEventRecord(c, st);
-    std::lock_guard<std::mutex> g(g_timing.mu);
-    g_timing.pending.push_back({a, b, c});
-  }
-};
-
-// ---------------------------------------------------------------------------
-// kernel sequence
-template <int DT>
-struct Runner {
-  static void delegate(const Plan& p, const uint32_t* keys, uint32_t* dkey, uint32_t* didx, Ctl* ctl,
-                       hipStream_t st, DirectOut out = DirectOut{nullptr, nullptr, nullptr, 0}) {
-    if (p.alpha >= 2) {
-      const unsigned g = (unsigned)((p.n + p.chunk - 1) / p.chunk);
-#define DRTOPK_DEL(B, V) \
-  hipLaunchKernelGGL((k_delegate<DT, B, V>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.chunk, dkey, didx, ctl, p.kD, \
-                     out)
-      switch (p.beta * 2 + (p.vec ? 1 : 0)) {
-        case 2: DRTOPK_DEL(1, false); break;
-        case 3: DRTOPK_DEL(1, true); break;
-        case 4: DRTOPK_DEL(2, false); break;
-        case 5: DRTOPK_DEL(2, true); break;
-        case 8: DRTOPK_DEL(4, false); break;
-        case 9: DRTOPK_DEL(4, true); break;
-        case 16: DRTOPK_DEL(8, false); break;
-        default: DRTOPK_DEL(8, true); break;
-      }
-#undef DRTOPK_DEL
-    } else {
-      const unsigned g = grid_for(p.S, 256, 4096);
-#define DRTOPK_DELT(B) \
-  hipLaunchKernelGGL((k_delegate_thread<DT, B>), dim3(g), dim3(256), 0, st, keys, p.n, p.alpha, p.S, dkey, didx, ctl, \
-                     p.kD, out)
-      switch (p.beta) {
-        case 1: DRTOPK_DELT(1); break;
-        case 2: DRTOPK_DELT(2); break;
-        case 4: DRTOPK_DELT(4); break;
-        default: DRTOPK_DELT(8); break;
-      }
-#undef DRTOPK_DELT
-    }
-  }
-
-  template <int B, bool V>
-  static void launch_tail_t(TailArgs& ta, hipStream_t st) {
-    static int blocks = 0;  // blocks that fit the device at once (phases need no co-residency)
-    if (blocks == 0) {
-      int dev = 0, cus = 0, per = 0;
-      (void)hipGetDevice(&dev);
-      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_tail<DT, B, V>),
-                                                          kTailThreads, 0);
-      if (per > 2) per = 2;
-      if (per < 1) per = 1;
-      blocks = cus * per;
-    }
-    hipLaunchKernelGGL((k_tail<DT, B, V>), dim3(blocks), dim3(kTailThreads), 0, st, ta);
-  }
-
-  static void launch_tail(const Plan& p, TailArgs& ta, hipStream_t st) {
-    switch (p.beta * 2 + (p.vec ? 1 : 0)) {
-      case 2: launch_tail_t<1, false>(ta, st); break;
-      case 3: launch_tail_t<1, true>(ta, st); break;
-      case 4: launch_tail_t<2, false>(ta, st); break;
-      case 5: launch_tail_t<2, true>(ta, st); break;
-      case 8: launch_tail_t<4, false>(ta, st); break;
-      case 9: launch_tail_t<4, true>(ta, st); break;
-      case 16: launch_tail_t<8, false>(ta, st); break;
-      default: launch_tail_t<8, true>(ta, st); break;
-    }
-  }
-
-  static void qualify(const Plan& p, uint32_t* dkey, uint32_t* didx, Ctl* ctl, uint32_t* Q, uint32_t* ckey,
-                      uint32_t* cidx, hipStream_t st) {
-    const unsigned g = grid_for(p.S, 256 * 16, 1024);
-    switch (p.beta) {
-      case 1: hipLaunchKernelGGL((k_qualify<1>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
-      case 2: hipLaunchKernelGGL((k_qualify<2>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
-      case 4: hipLaunchKernelGGL((k_qualify<4>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
-      default: hipLaunchKernelGGL((k_qualify<8>), dim3(g), dim3(256), 0, st, dkey, didx, p.S, ctl, Q, ckey, cidx); break;
-    }
-  }
-
-  // The k sorted outputs from okey/oidx (exactly k entries), k > kSmallCap.
-  // gated: 0 always run, 1 only if the tail kernel set ctl->need_merge
-  static void big_sort(const Plan& p, void* ws, uint32_t* out_vals, uint32_t* out_idx, uint32_t* out_kth,
-                       int gated, Ctl* ctl, hipStream_t st) {
-    uint64_t* A = at<uint64_t>(ws, p.off_A);
-    uint64_t* B = at<uint64_t>(ws, p.off_B);
-    hipLaunchKernelGGL(k_blocksort, dim3((unsigned)(p.M / kSortTile)), dim3(1024), 0, st,
-                       at<uint32_t>(ws, p.off_okey), at<uint32_t>(ws, p.off_oidx), p.k, A, gated, ctl);
-    for (uint64_t run = kSortTile; run < p.M; run <<= 1) {
-      const int last = (2 * run == p.M) ? 1 : 0;
-      hipLaunchKernelGGL((k_merge<DT>), dim3((unsigned)(p.M / 256)), dim3(256), 0, st, A, B, p.M, run, last, p.k,
-                         out_vals, out_idx, out_kth, gated, ctl);
-      std::swap(A, B);
-    }
-  }
-
-  // filter_only: stop once the survivors are known (stage checks).
-  static void run(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
-                  uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st) {
-    PhaseMarks pm;
-    pm.begin(st);
-    run_inner(p, keys, ws, out_vals, out_idx, out_kth, kth_only, filter_only, st, pm);
-    pm.end(st);
-  }
-
-  static void run_inner(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
-                        uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st, PhaseMarks& pm) {
-    Ctl* ctl = at<Ctl>(ws, p.off_ctl);
-    hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, st, ctl, (uint32_t)p.S, (uint32_t)p.cap_c,
-                       p.all ? 1u : 0u);
-    pm.start(st);
-    uint32_t* okey = at<uint32_t>(ws, p.off_okey);
-    uint32_t* oidx = at<uint32_t>(ws, p.off_oidx);
-    const uint32_t k = p.k;
-    if (p.mode == 1 && p.variant == 0) {
-      uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
-      uint32_t* didx = at<uint32_t>(ws, p.off_didx);
-      if (k == 1 && !filter_only) {  // the largest delegate is the answer (Rule 1)
-        delegate(p, keys, dkey, didx, ctl, st, DirectOut{out_vals, out_idx, out_kth, 1});
-        pm.mid(st);
-        return;
-      }
-      delegate(p, keys, dkey, didx, ctl, st);
-      pm.mid(st);
-      TailArgs ta;
-      ta.keys = keys;
-      ta.n = p.n;
-      ta.alpha = p.alpha;
-      ta.S = p.S;
-      ta.nd = p.nd;
-      ta.k = k;
-      ta.kD = p.kD;
-      ta.slack = p.slack;
-      ta.all = p.all ? 1 : 0;
-      ta.kth_only = kth_only ? 1 : 0;
-      ta.stop_after_scan = filter_only ? 1 : 0;
-      ta.big_sort = (!kth_only && k > (uint32_t)kSmallCap) ? 1 : 0;
-      ta.dkey = dkey;
-      ta.didx = didx;
-      ta.Q = at<uint32_t>(ws, p.off_q);
-      ta.ckey = at<uint32_t>(ws, p.off_ckey);
-      ta.cidx = at<uint32_t>(ws, p.off_cidx);
-      ta.skey = at<uint32_t>(ws, p.off_skey);
-      ta.sidx = at<uint32_t>(ws, p.off_sidx);
-      ta.okey = okey;
-      ta.oidx = oidx;
-      ta.cap_s = (uint32_t)p.cap_c;
-      ta.out_vals = out_vals;
-      ta.out_idx = out_idx;
-      ta.out_kth = out_kth;
-      ta.ctl = ctl;
-      launch_tail(p, ta, st);
-      // the merge sort runs only if the tail fell back to its select path
-      if (ta.big_sort && !filter_only) big_sort(p, ws, out_vals, out_idx, out_kth, 1, ctl, st);
-      return;
-    }
-    if (p.mode == 1) {
-      uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
-      uint32_t* didx = at<uint32_t>(ws, p.off_didx);
-      uint32_t* Q = at<uint32_t>(ws, p.off_q);
-      uint32_t* ckey = at<uint32_t>(ws, p.off_ckey);
-      uint32_t* cidx = at<uint32_t>(ws, p.off_cidx);
-      delegate(p, keys, dkey, didx, ctl, st);
-      pm.mid(st);
-      const unsigned gD = grid_for(p.nd, 256 * 8, 1024);
-      for (int pass = 1; pass < kPasses; ++pass)
-        hipLaunchKernelGGL((k_pass<SRC_D, DT>), dim3(gD), dim3(256), 0, st, dkey, didx, p.nd, pass, 0, ctl, p.kD);
-      qualify(p, dkey, didx, ctl, Q, ckey, cidx, st);
-      // expected concatenated length: about k/beta subranges of 2^alpha (grid-stride covers more)
-      const unsigned gS = grid_for(((uint64_t)((k - 1) / p.beta) + 1) << p.alpha, 4096, 2048);
-      if (p.vec)
-        hipLaunchKernelGGL((k_scan<DT, true>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
-      else
-        hipLaunchKernelGGL((k_scan<DT, false>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
-      if (filter_only) return;
-      const bool may_be_big = p.cap_c > (uint64_t)kSmallCap;
-      hipLaunchKernelGGL((k_final_small<SRC_C, DT>), dim3(1), dim3(1024), 0, st, ckey, cidx, (uint64_t)0,
-                         may_be_big ? 1 : 0, k, ctl, out_vals, out_idx, out_kth);
-      if (!may_be_big) return;
-      const unsigned gC = grid_for(p.cap_c, 256 * 8, 1024);
-      for (int pass = 0; pass < kPasses; ++pass)
-        hipLaunchKernelGGL((k_pass<SRC_C, DT>), dim3(gC), dim3(256), 0, st, ckey, cidx, (uint64_t)0, pass, 2, ctl, k);
-      if (kth_only) {
-        hipLaunchKernelGGL((k_kth_from_sel<DT>), dim3(1), dim3(64), 0, st, 2, ctl, out_kth);
-        return;
-      }
-      hipLaunchKernelGGL((k_compact<SRC_C, DT>), dim3(gC), dim3(256), 0, st, ckey, cidx, (uint64_t)0, 2, k, ctl, okey,
-                         oidx);
-      if (k <= (uint32_t)kSmallCap)
-        hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 2, k,
-                           ctl, out_vals, out_idx, out_kth);
-      else
-        big_sort(p, ws, out_vals, out_idx, out_kth, 0, ctl, st);
-    } else {
-      if (p.n <= (uint64_t)kSmallCap) {
-        hipLaunchKernelGGL((k_final_small<SRC_V, DT>), dim3(1), dim3(1024), 0, st, keys, (const uint32_t*)nullptr,
-                           p.n, 0, k, ctl, out_vals, out_idx, out_kth);
-        return;
-      }
-      const unsigned gV = grid_for(p.n, 256 * 16, 2048);
-      for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL((k_pass<SRC_V, DT>), dim3(gV), dim3(256), 0, st, keys, (const uint32_t*)nullptr, p.n, pass,
-                           0, ctl, k);
-        if (pass == 0) pm.mid(st);
-      }
-      if (kth_only) {
-        hipLaunchKernelGGL((k_kth_from_sel<DT>), dim3(1), dim3(64), 0, st, 0, ctl, out_kth);
-        return;
-      }
-      hipLaunchKernelGGL((k_compact<SRC_V, DT>), dim3(gV), dim3(256), 0, st, keys, (const uint32_t*)nullptr, p.n, 0,
-                         k, ctl, okey, oidx);
-      if (k <= (uint32_t)kSmallCap)
-        hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 0, k,
-                           ctl, out_vals, out_idx, out_kth);
-      else
-        big_sort(p, ws, out_vals, out_idx, out_kth, 0, ctl, st);
-    }
-  }
-};
-
-template <int DT>
-__global__ void k_decode_inplace(uint32_t* v, uint64_t m) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
-    v[i] = dec<DT>(v[i]);
+int dt_code(int dtype) {
+  const int base = dtype & ~DRTOPK_SMALLEST;
+  const int t = base == DRTOPK_F32 ? DT_F32 : base == DRTOPK_I32 ? DT_I32 : DT_U32;
+  return t | ((dtype & DRTOPK_SMALLEST) ? DT_MIN : 0);
 }
 
 int check_args(const void* keys, uint64_t n, uint32_t k, int dtype) {
   if (!keys) return DRTOPK_EINVAL;
   if (n == 0 || n >= (1ull << 32)) return DRTOPK_EINVAL;
   if (k == 0 || (uint64_t)k > n) return DRTOPK_EINVAL;
-  if (dtype != DRTOPK_U32 && dtype != DRTOPK_F32) return DRTOPK_EINVAL;
+  if (!dtype_ok(dtype)) return DRTOPK_EINVAL;
   return DRTOPK_OK;
 }
 
-uint32_t host_dec(int dt, uint32_t u) { return dt == DT_F32 ? u ^ (((u >> 31) - 1u) | 0x80000000u) : u; }
+// Input bit pattern of an encoded key (the inverse of enc<DT>, on the host).
+uint32_t host_dec(int code, uint32_t u) {
+  if (code & DT_MIN) u = ~u;
+  switch (code & 3) {
+    case DT_F32: return u ^ (((u >> 31) - 1u) | 0x80000000u);
+    case DT_I32: return u ^ 0x80000000u;
+    default: return u;
+  }
+}
 
 // Runs the whole path; `fn` (optional) runs under the workspace lock after the
 // enqueue, with the plan and workspace pointer.
@@ -596,7 +338,7 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
     d.keys = kp;
     d.n = n;
     d.k = k;
-    d.dtype = dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
+    d.dtype = (uint32_t)dt_code(dtype);
     d.alpha = (uint32_t)p.alpha;
     d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
     d.out_idx = kth_only ? nullptr : out_idx;
@@ -605,12 +347,10 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
     if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
     return after(p, ws->ptr, s);
   }
-  if (dtype == DRTOPK_F32)
-    Runner<DT_F32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
-                        kth_only, filter_only, s);
-  else
-    Runner<DT_U32>::run(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx, static_cast<uint32_t*>(out_kth),
-                        kth_only, filter_only, s);
+  with_codec(dt_code(dtype), [&](auto c) {
+    run_codec<decltype(c)::value>(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx,
+                                  static_cast<uint32_t*>(out_kth), kth_only, filter_only, s);
+  });
   const hipError_t le = tl_launch_err;
   tl_launch_err = hipSuccess;
   if (hipGetLastError() != hipSuccess || le != hipSuccess) return DRTOPK_EDEVICE;
@@ -645,7 +385,7 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
   d.keys = static_cast<const uint32_t*>(q.keys);
   d.n = q.n;
   d.k = q.k;
-  d.dtype = q.dtype == DRTOPK_F32 ? DT_F32 : DT_U32;
+  d.dtype = (uint32_t)dt_code((int)q.dtype);
   d.alpha = (uint32_t)batched_alpha(q.n, q.k);
   d.out_vals = static_cast<uint32_t*>(q.out_vals);
   d.out_idx = q.out_idx;
@@ -772,7 +512,7 @@ int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   stats->delegates = p.nd;
   stats->scanned = h.nq;
   stats->candidates = p.mode == 1 ? h.nc : p.n;
-  stats->t_key_bits = p.mode == 1 ? host_dec(p.dt, (uint32_t)(h.selD.prefix >> 32)) : 0;
+  stats->t_key_bits = p.mode == 1 ? host_dec(dt_code(p.dt), (uint32_t)(h.selD.prefix >> 32)) : 0;
   stats->t_idx = p.mode == 1 ? ~(uint32_t)h.selD.prefix : 0;
   const uint64_t t0 = h.tstamp[kPhases + 1];
   for (int i = 0; i < kPhases && i < 20; ++i)
@@ -928,14 +668,8 @@ int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int bet
   Ctl* ctl = at<Ctl>(ws->ptr, p.off_ctl);
   const uint32_t* kp = static_cast<const uint32_t*>(keys);
   uint32_t* dk = static_cast<uint32_t*>(out_dkeys);
-  hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, s, ctl, (uint32_t)p.S, (uint32_t)p.cap_c, 0u);
-  const unsigned g = grid_for(p.nd, 256 * 4, 4096);
-  if (dtype == DRTOPK_F32) {
-    Runner<DT_F32>::delegate(p, kp, dk, out_didx, ctl, s);
-    hipLaunchKernelGGL((k_decode_inplace<DT_F32>), dim3(g), dim3(256), 0, s, dk, p.nd);
-  } else {
-    Runner<DT_U32>::delegate(p, kp, dk, out_didx, ctl, s);
-  }
+  with_codec(dt_code(dtype),
+             [&](auto c) { delegates_codec<decltype(c)::value>(p, kp, dk, out_didx, ctl, s); });
   if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
   return DRTOPK_OK;
 }
@@ -957,7 +691,7 @@ int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int a
                           if (hipMemcpy(&t, &at<Ctl>(ws, p.off_ctl)->selD.prefix, 8, hipMemcpyDeviceToHost) !=
                               hipSuccess)
                             return (int)DRTOPK_EDEVICE;
-                          t_out[0] = host_dec(p.dt, (uint32_t)(t >> 32));
+                          t_out[0] = host_dec(dt_code(p.dt), (uint32_t)(t >> 32));
                           t_out[1] = ~(uint32_t)t;
                         }
                         *count = nc;

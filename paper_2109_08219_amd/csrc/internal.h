@@ -8,6 +8,8 @@
 // elements are distinct, and the paper's Rules 1-3 hold exactly.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -20,7 +22,8 @@ constexpr int kPasses = 6;        // 64-bit composite = 11+11+10 key bits, 11+11
 constexpr int kSmallCap = 8192;   // candidate counts sorted by one workgroup in LDS
 constexpr int kSortTile = 4096;   // block-sort tile of the large-k output sort
 
-enum { DT_U32 = 0, DT_F32 = 1 };
+// Key codecs: bits 0-1 the key type, DT_MIN set = the k smallest first.
+enum { DT_U32 = 0, DT_F32 = 1, DT_I32 = 2, DT_MIN = 4 };
 enum { SRC_D = 0, SRC_C = 1, SRC_V = 2, SRC_OUT = 3 };
 
 __host__ __device__ constexpr int pass_shift(int p) {
@@ -96,16 +99,39 @@ struct Ctl {
 __device__ __forceinline__ uint32_t clamp_nc(const Ctl* c) { return c->nc < c->cap_c ? c->nc : c->cap_c; }
 __device__ __forceinline__ uint32_t clamp_nq(const Ctl* c) { return c->nq < c->cap_q ? c->nq : c->cap_q; }
 
-// Order-preserving uint32 encoding of the input bit patterns.
+// Order-preserving uint32 encoding of the input bit patterns: the larger
+// encoding ranks first.  float32 by IEEE totalOrder (negative patterns have
+// every bit flipped, non-negative ones the sign bit), int32 with the sign bit
+// flipped; for the k smallest the encoding is complemented, so the same
+// kernels select them (ties still go to the lower position).
 template <int DT>
 __device__ __forceinline__ uint32_t enc(uint32_t b) {
-  if constexpr (DT == DT_U32) return b;
-  else return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+  uint32_t e;
+  if constexpr ((DT & 3) == DT_U32) e = b;
+  else if constexpr ((DT & 3) == DT_F32) e = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+  else e = b ^ 0x80000000u;
+  if constexpr ((DT & DT_MIN) != 0) e = ~e;
+  return e;
 }
 template <int DT>
 __device__ __forceinline__ uint32_t dec(uint32_t u) {
-  if constexpr (DT == DT_U32) return u;
-  else return u ^ (((u >> 31) - 1u) | 0x80000000u);
+  if constexpr ((DT & DT_MIN) != 0) u = ~u;
+  if constexpr ((DT & 3) == DT_U32) return u;
+  else if constexpr ((DT & 3) == DT_F32) return u ^ (((u >> 31) - 1u) | 0x80000000u);
+  else return u ^ 0x80000000u;
+}
+
+// Calls f(std::integral_constant<int, DT>{}) for a codec (0..2, 4..6).
+template <typename F>
+__host__ __device__ __forceinline__ void with_codec(int code, F&& f) {
+  switch (code) {
+    case DT_F32: f(std::integral_constant<int, DT_F32>{}); break;
+    case DT_I32: f(std::integral_constant<int, DT_I32>{}); break;
+    case DT_U32 | DT_MIN: f(std::integral_constant<int, DT_U32 | DT_MIN>{}); break;
+    case DT_F32 | DT_MIN: f(std::integral_constant<int, DT_F32 | DT_MIN>{}); break;
+    case DT_I32 | DT_MIN: f(std::integral_constant<int, DT_I32 | DT_MIN>{}); break;
+    default: f(std::integral_constant<int, DT_U32>{}); break;
+  }
 }
 
 __device__ __forceinline__ uint64_t comp(uint32_t key, uint32_t pos) {

@@ -746,7 +746,7 @@ __global__ void k_kth_from_sel(int gate, Ctl* ctl, uint32_t* out_kth) {
 }
 
 // Sort tiles of kSortTile composites in LDS (descending); pads are 0.
-__global__ __launch_bounds__(1024) void k_blocksort(const uint32_t* __restrict__ okey,
+static __global__ __launch_bounds__(1024) void k_blocksort(const uint32_t* __restrict__ okey,
                                                     const uint32_t* __restrict__ oidx, uint32_t k,
                                                     uint64_t* __restrict__ A, int gated, const Ctl* ctl) {
   __shared__ uint64_t buf[kSortTile];
@@ -805,7 +805,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ A, u
   }
 }
 
-__global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t all) {
+static __global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t all) {
   uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
   const uint32_t nw = offsetof(Ctl, cap_q) / 4;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) w[i] = 0;

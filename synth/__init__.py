@@ -157,15 +157,26 @@ def derive_seed(base: int, i: int) -> int:
 
 
 def keys(kind: str, n: int, seed: int = DEFAULT_SEED) -> tuple[np.ndarray, str]:
-    """Named workloads -> (array, dtype tag 'u32' or 'f32')."""
+    """Named workloads -> (array, dtype tag 'u32', 'f32' or 'i32').
+
+    uniform_i32 is the uniform uint32 stream read as int32 (uniform over the
+    whole signed range); smallrange_i32 maps it onto [-1000, 1000] (ties and
+    negatives everywhere); revsorted_f32 is the sorted normal sample in
+    descending order (the adversarial layout for the k smallest)."""
     if kind == "uniform_u32":
         return uniform_u32(n, seed), "u32"
     if kind == "normal_f32":
         return normal_f32(n, seed), "f32"
     if kind == "sorted_f32":
         return sorted_normal_f32(n, seed), "f32"
+    if kind == "revsorted_f32":
+        return sorted_normal_f32(n, seed)[::-1].copy(), "f32"
     if kind == "heavydup_u32":
         return heavy_dup_u32(n, seed), "u32"
+    if kind == "uniform_i32":
+        return uniform_u32(n, seed).view(np.int32), "i32"
+    if kind == "smallrange_i32":
+        return (heavy_dup_u32(n, seed, 2001).astype(np.int64) - 1000).astype(np.int32), "i32"
     raise ValueError(f"unknown workload kind {kind!r}")
 
 

@@ -62,6 +62,18 @@ def test_argument_errors_without_gpu(n, k, dtype):
     assert L.kth_select(dummy, n, k, dtype, out, None) == 1
 
 
+def test_dtype_codes_without_gpu():
+    """int32 keys and the k-smallest flag are valid with every key type; other codes are not."""
+    L = drt.lib()
+    o = drt.Options()
+    for code in (0, 1, 2, 0x100, 0x101, 0x102):
+        assert L.drtopk_plan(1 << 20, 100, code, ctypes.byref(o)) == 0, code
+    for code in (3, 4, 0x103, 0x200, 0x300, -1):
+        assert L.drtopk_plan(1 << 20, 100, code, ctypes.byref(o)) == 1, code
+    assert drt.plan(1 << 20, 100, "i32-min") == drt.plan(1 << 20, 100, "u32")
+    assert drt.footprint(1 << 24, 1000, "f32-min") == drt.footprint(1 << 24, 1000, "f32")
+
+
 def test_null_pointers_rejected():
     L = drt.lib()
     assert L.topk_select(None, 10, 1, 0, ctypes.c_void_p(32), None, None) == 1
