@@ -142,6 +142,24 @@ def bench_small(drt, synth, torch, args):
     return r
 
 
+def bench_smallest_i32(drt, torch, t_u, t_f):
+    """The k smallest and int32 keys at N = 2^30, on the step's own inputs: float32
+    N(0,1) smallest first, and the uniform uint32 stream read as int32 (uniform over
+    the signed range), largest and smallest first."""
+    out = []
+    for name, t, ks, largest in (("f32", t_f, KS, False), ("i32", t_u.view(torch.int32), (1024,), True),
+                                 ("i32", t_u.view(torch.int32), (1024,), False)):
+        for k in ks:
+            v = torch.empty(k, dtype=t.dtype, device="cuda")
+            ix = torch.empty(k, dtype=torch.int32, device="cuda")
+            r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix, largest=largest), 10, 2)
+            _, _, st = drt.topk_select(t, k, v, ix, largest=largest, stats=True)
+            r.update(dtype=name, order="largest" if largest else "smallest", k=k, alpha=st.alpha, beta=st.beta,
+                     keys_per_s=t.numel() / (r["ms_median"] / 1e3))
+            out.append(r)
+    return out
+
+
 def bench_adversarial(drt, torch, args):
     """N = 2^29, k = 16384: float32 N(0,1) sorted ascending (beta 1, 2, 4, 8) and uint32
     uniform over [0, 16) (planner's choice).  Inputs drawn on the GPU."""
@@ -342,7 +360,9 @@ def main() -> int:
                          f"numpy selection oracle (single-threaded partition + sort), {t_cpu:.1f} s"}
 
     case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
-    del cases, t_u, t_f
+    del cases
+    smallest_i32 = bench_smallest_i32(drt, torch, t_u, t_f)
+    del t_u, t_f
     torch.cuda.empty_cache()
     small = bench_small(drt, synth, torch, args)
     adversarial = None if args.no_adversarial else bench_adversarial(drt, torch, args)
@@ -374,6 +394,7 @@ def main() -> int:
                      "probe_read_GBps": probe_GBps, "frac_of_probe": achieved / probe_GBps},
         "cpu_baseline": cpu,
         "small_case": small,
+        "smallest_and_i32": smallest_i32,
         "adversarial": adversarial,
         "batched": batched,
         "serving": serving,
