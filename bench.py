@@ -160,6 +160,25 @@ def bench_smallest_i32(drt, torch, t_u, t_f):
     return out
 
 
+def bench_delegates_vs_plain(drt, torch, t_u):
+    """The paper's claim that delegates speed up the radix top-k they wrap: at
+    N = 2^28 uint32 uniform, the delegate method (planner's alpha, beta) against
+    the plain radix select over all keys (mode 2), k = 2^0 .. 2^20."""
+    t = t_u[: 1 << 28]
+    out = []
+    for lg_k in (0, 4, 8, 10, 12, 14, 16, 18, 20):
+        k = 1 << lg_k
+        v = torch.empty(k, dtype=t.dtype, device="cuda")
+        ix = torch.empty(k, dtype=torch.int32, device="cuda")
+        row = {"k": k}
+        for name, mode in (("delegates", 1), ("plain_radix", 2)):
+            r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix, mode=mode), 5, 1)
+            row[name + "_ms"] = r["ms_median"]
+        row["speedup"] = row["plain_radix_ms"] / row["delegates_ms"]
+        out.append(row)
+    return out
+
+
 def bench_adversarial(drt, torch, args):
     """N = 2^29, k = 16384: float32 N(0,1) sorted ascending (beta 1, 2, 4, 8) and uint32
     uniform over [0, 16) (planner's choice).  Inputs drawn on the GPU."""
@@ -362,6 +381,7 @@ def main() -> int:
     case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
     del cases
     smallest_i32 = bench_smallest_i32(drt, torch, t_u, t_f)
+    by_k = bench_delegates_vs_plain(drt, torch, t_u)
     del t_u, t_f
     torch.cuda.empty_cache()
     small = bench_small(drt, synth, torch, args)
@@ -395,6 +415,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "small_case": small,
         "smallest_and_i32": smallest_i32,
+        "delegates_vs_plain_radix": by_k,
         "adversarial": adversarial,
         "batched": batched,
         "serving": serving,
