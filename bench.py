@@ -27,6 +27,9 @@ its timed region:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-adversarial] [--no-batched] [--no-serving] [--copy-calibration]
+       python bench.py --delegate-vector A:B[,A:B...]
+                       (profiling aid: only the delegate vector of the 2^30 uniform input for
+                       each (alpha, beta), twice each, then exit; no JSON line)
 """
 from __future__ import annotations
 
@@ -253,6 +256,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adversarial", action="store_true")
+    ap.add_argument("--delegate-vector", default=None, metavar="A:B,...",
+                    help="only build the delegate vector for these (alpha, beta) pairs (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, whose HBM counters calibrate the traffic figure")
     args = ap.parse_args()
@@ -270,6 +275,17 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.delegate_vector:
+        x_u = synth.uniform_u32(N, synth.DEFAULT_SEED)
+        t_u = torch.from_numpy(x_u).to(dev)
+        del x_u
+        for pair in args.delegate_vector.split(","):
+            a, b = (int(v) for v in pair.split(":"))
+            for _ in range(2):
+                drt.delegates(t_u, a, b)
+            torch.cuda.synchronize()
+            print(f"[bench] delegate vector alpha {a} beta {b} done", file=sys.stderr, flush=True)
+        return 0
     print(f"[bench] generating 2 x 2^30 keys", file=sys.stderr, flush=True)
     x_u = synth.uniform_u32(N, synth.DEFAULT_SEED)
     t_u = torch.from_numpy(x_u).to(dev)
