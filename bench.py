@@ -26,7 +26,8 @@ its timed region:
            queries/s and p50/p99 latency (arrival -> completion on the host).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-adversarial] [--no-batched] [--no-serving] [--copy-calibration]
+                       [--no-adversarial] [--no-batched] [--no-serving] [--no-smallest] [--no-by-k]
+                       [--copy-calibration]
        python bench.py --delegate-vector A:B[,A:B...]
                        (profiling aid: only the delegate vector of the 2^30 uniform input for
                        each (alpha, beta), twice each, then exit; no JSON line)
@@ -256,6 +257,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adversarial", action="store_true")
+    ap.add_argument("--no-smallest", action="store_true", help="skip the k smallest / int32 cases")
+    ap.add_argument("--no-by-k", action="store_true", help="skip delegates against the plain radix select")
     ap.add_argument("--delegate-vector", default=None, metavar="A:B,...",
                     help="only build the delegate vector for these (alpha, beta) pairs (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -396,8 +399,8 @@ def main() -> int:
 
     case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
     del cases
-    smallest_i32 = bench_smallest_i32(drt, torch, t_u, t_f)
-    by_k = bench_delegates_vs_plain(drt, torch, t_u)
+    smallest_i32 = None if args.no_smallest else bench_smallest_i32(drt, torch, t_u, t_f)
+    by_k = None if args.no_by_k else bench_delegates_vs_plain(drt, torch, t_u)
     del t_u, t_f
     torch.cuda.empty_cache()
     small = bench_small(drt, synth, torch, args)
