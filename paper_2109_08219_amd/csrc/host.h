@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "drtopk.h"
@@ -82,6 +83,20 @@ struct PhaseMarks {
     g_timing.pending.push_back({a, b, c});
   }
 };
+
+// Calls f(std::integral_constant<int, DT>{}) for a codec (0..2, 4..6): the
+// host-side dispatch to the per-codec translation units.
+template <typename F>
+inline void with_codec(int code, F&& f) {
+  switch (code) {
+    case DT_F32: f(std::integral_constant<int, DT_F32>{}); break;
+    case DT_I32: f(std::integral_constant<int, DT_I32>{}); break;
+    case DT_U32 | DT_MIN: f(std::integral_constant<int, DT_U32 | DT_MIN>{}); break;
+    case DT_F32 | DT_MIN: f(std::integral_constant<int, DT_F32 | DT_MIN>{}); break;
+    case DT_I32 | DT_MIN: f(std::integral_constant<int, DT_I32 | DT_MIN>{}); break;
+    default: f(std::integral_constant<int, DT_U32>{}); break;
+  }
+}
 
 // The whole single-problem path for plan p on codec DT (enqueue only).
 template <int DT>

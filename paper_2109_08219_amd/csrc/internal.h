@@ -121,18 +121,6 @@ __device__ __forceinline__ uint32_t dec(uint32_t u) {
   else return u ^ 0x80000000u;
 }
 
-// Calls f(std::integral_constant<int, DT>{}) for a codec (0..2, 4..6).
-template <typename F>
-__host__ __device__ __forceinline__ void with_codec(int code, F&& f) {
-  switch (code) {
-    case DT_F32: f(std::integral_constant<int, DT_F32>{}); break;
-    case DT_I32: f(std::integral_constant<int, DT_I32>{}); break;
-    case DT_U32 | DT_MIN: f(std::integral_constant<int, DT_U32 | DT_MIN>{}); break;
-    case DT_F32 | DT_MIN: f(std::integral_constant<int, DT_F32 | DT_MIN>{}); break;
-    case DT_I32 | DT_MIN: f(std::integral_constant<int, DT_I32 | DT_MIN>{}); break;
-    default: f(std::integral_constant<int, DT_U32>{}); break;
-  }
-}
 
 __device__ __forceinline__ uint64_t comp(uint32_t key, uint32_t pos) {
   return ((uint64_t)key << 32) | (uint64_t)(~pos);
