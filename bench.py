@@ -164,6 +164,22 @@ def bench_smallest_i32(drt, torch, t_u, t_f):
     return out
 
 
+def bench_shard(drt, torch, t_u, t_f):
+    """One GPU's share of an 8-way sharded N = 2^30 call, at its real shape: the first
+    2^27 keys of each input, the step's k values (the local top-k each GPU would
+    contribute before the all-gather)."""
+    out = []
+    for name, t in (("u32", t_u[: 1 << 27]), ("f32", t_f[: 1 << 27])):
+        for k in KS:
+            v = torch.empty(k, dtype=t.dtype, device="cuda")
+            ix = torch.empty(k, dtype=torch.int32, device="cuda")
+            r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix), 10, 3)
+            r.update(dtype=name, k=k, keys_per_s=t.numel() / (r["ms_median"] / 1e3),
+                     GBps=4 * t.numel() / (r["ms_median"] / 1e3) / 1e9)
+            out.append(r)
+    return out
+
+
 def bench_delegates_vs_plain(drt, torch, t_u):
     """The paper's claim that delegates speed up the radix top-k they wrap: at
     N = 2^28 uint32 uniform, the delegate method (planner's alpha, beta) against
@@ -258,7 +274,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adversarial", action="store_true")
     ap.add_argument("--no-smallest", action="store_true", help="skip the k smallest / int32 cases")
-    ap.add_argument("--no-by-k", action="store_true", help="skip delegates against the plain radix select")
+    ap.add_argument("--no-by-k", action="store_true",
+                    help="skip delegates against the plain radix select and the 2^27 shard cases")
     ap.add_argument("--delegate-vector", default=None, metavar="A:B,...",
                     help="only build the delegate vector for these (alpha, beta) pairs (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -401,6 +418,7 @@ def main() -> int:
     del cases
     smallest_i32 = None if args.no_smallest else bench_smallest_i32(drt, torch, t_u, t_f)
     by_k = None if args.no_by_k else bench_delegates_vs_plain(drt, torch, t_u)
+    shard = None if args.no_by_k else bench_shard(drt, torch, t_u, t_f)
     del t_u, t_f
     torch.cuda.empty_cache()
     small = bench_small(drt, synth, torch, args)
@@ -435,6 +453,7 @@ def main() -> int:
         "small_case": small,
         "smallest_and_i32": smallest_i32,
         "delegates_vs_plain_radix": by_k,
+        "shard_2p27": shard,
         "adversarial": adversarial,
         "batched": batched,
         "serving": serving,
