@@ -267,6 +267,25 @@ int drtopk_server_replay(drtopk_server_t* server, const drtopk_problem_t* reqs, 
  * DRTOPK_ENOMEM and later submits return DRTOPK_ENOMEM. */
 int drtopk_server_destroy(drtopk_server_t* server);
 
+/* Top-k over keys in HOST memory, streamed through the device in chunks: for
+ * inputs larger than the device memory (the paper's reload of sub-vectors
+ * that do not fit one GPU, Section 5.4).  Each chunk's top-k (positions
+ * offset to the whole input) is merged with the running top-k by a top-k over
+ * the two lists (running list first: it holds the lower positions, so the tie
+ * rule carries over); copies of the next chunk overlap the current chunk's
+ * selection (two device buffers, a copy stream of default priority).
+ *   host_keys  host memory (pageable or pinned), n keys of `dtype`
+ *   n, k, dtype as for topk_select (DRTOPK_SMALLEST allowed)
+ *   chunk      keys per transfer; 0 = min(n, 2^26); at most n
+ *   out_vals / out_idx  device memory, as for topk_select (out_idx may be NULL)
+ * Allocates device buffers for two chunks and the candidate lists, and
+ * returns once the result is complete (it synchronises `stream`), so the
+ * host buffer may be reused on return.  DRTOPK_EINVAL on bad arguments,
+ * DRTOPK_ENOMEM if the buffers cannot be allocated, DRTOPK_EDEVICE if a copy
+ * or launch fails. */
+int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, uint64_t chunk, void* out_vals,
+                     uint32_t* out_idx, void* stream);
+
 /* Measurement helper: reads keys[0 .. n - n mod 2^20) once with the delegate
  * pass's access pattern and launch geometry (4 MiB per workgroup, 16-byte
  * non-temporal loads, eight in flight per lane) and writes their maximum to

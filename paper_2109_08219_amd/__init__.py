@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
             "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
             "drtopk_footprint": [u64, u32, i32, ctypes.POINTER(u64)],
             "drtopk_read_probe": [vp, u64, vp, vp],
+            "topk_select_host": [vp, u64, u32, i32, u64, vp, vp, vp],
             "drtopk_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "drtopk_server_submit": [vp, ctypes.POINTER(Problem), ctypes.POINTER(u64)],
             "drtopk_server_wait": [vp, u64, ctypes.POINTER(ctypes.c_double)],
@@ -438,6 +439,30 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def topk_select_host(keys, k: int, *, chunk: int = 0, largest: bool = True, dtype=None, stream=None):
+    """Top-k of a numpy array in host memory (uint32 / int32 / float32), streamed
+    through the device in chunks of `chunk` keys (0 = library choice).  Returns
+    (values, indices) as device tensors, like topk_select; synchronises `stream`."""
+    import numpy as np
+    torch = _torch()
+    keys = np.ascontiguousarray(keys)
+    if keys.ndim != 1 or keys.itemsize != 4:
+        raise ValueError("keys must be a 1-D array of 4-byte elements")
+    if dtype is None:
+        dtype = {np.dtype(np.uint32): "u32", np.dtype(np.float32): "f32", np.dtype(np.int32): "i32"}.get(keys.dtype)
+        if dtype is None:
+            raise TypeError(f"keys must be uint32, int32 or float32 (got {keys.dtype})")
+    code = _DTYPES[dtype] | (0 if largest else SMALLEST)
+    tdt = {"u32": torch.uint32, "f32": torch.float32, "i32": torch.int32}[dtype]
+    out_vals = torch.empty(k, dtype=tdt, device="cuda")
+    out_idx = torch.empty(k, dtype=torch.int32, device="cuda")
+    rc = lib().topk_select_host(ctypes.c_void_p(keys.ctypes.data), keys.shape[0], k, code, chunk,
+                                ctypes.c_void_p(out_vals.data_ptr()), ctypes.c_void_p(out_idx.data_ptr()),
+                                _stream(stream))
+    _check(rc, "topk_select_host")
+    return out_vals, out_idx
 
 
 def read_probe(keys, out=None, *, stream=None):

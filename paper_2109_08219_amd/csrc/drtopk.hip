@@ -486,6 +486,29 @@ __global__ __launch_bounds__(256) void k_read_probe(const uint32_t* __restrict__
   if (lane == 0) atomicMax(out, m);
 }
 
+// Streaming top-k (host input): candidates = running list (r entries) then
+// the chunk's list (c entries, positions + off), in that order.
+__global__ void k_stream_concat(const uint32_t* rv, const uint32_t* ri, uint32_t r, const uint32_t* cv,
+                                const uint32_t* ci, uint32_t c, uint64_t off, uint32_t* kv, uint32_t* ki) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < r + c; i += gridDim.x * blockDim.x) {
+    if (i < r) {
+      kv[i] = rv[i];
+      ki[i] = ri[i];
+    } else {
+      kv[i] = cv[i - r];
+      ki[i] = (uint32_t)(ci[i - r] + off);
+    }
+  }
+}
+// New running list: the selected candidates' values and whole-input positions.
+__global__ void k_stream_gather(const uint32_t* sv, const uint32_t* si, uint32_t m, const uint32_t* ki,
+                                uint32_t* rv, uint32_t* ri) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    rv[i] = sv[i];
+    ri[i] = ki[si[i]];
+  }
+}
+
 __global__ void k_zero_word(uint32_t* p) {
   if (threadIdx.x == 0) *p = 0;
 }
@@ -796,6 +819,84 @@ int drtopk_read_probe(const void* keys, uint64_t n, uint32_t* out_max, void* str
   hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(64), 0, s, out_max);
   hipLaunchKernelGGL(k_read_probe, dim3(g), dim3(256), 0, s, static_cast<const uint32_t*>(keys), n, chunk, out_max);
   return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+}
+
+int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, uint64_t chunk, void* out_vals,
+                     uint32_t* out_idx, void* stream) {
+  if (!out_vals) return DRTOPK_EINVAL;
+  int st = check_args(host_keys, n, k, dtype);
+  if (st) return st;
+  if (chunk == 0) chunk = n < (1ull << 26) ? n : (1ull << 26);
+  if (chunk > n) return DRTOPK_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
+  // device buffers: two chunks, the chunk's top-k, the running list, 2k candidates and the selection
+  const uint64_t kk = k;
+  const size_t bytes = 2 * chunk * 4 + (2 * kk + 2 * kk + 4 * kk + 2 * kk) * 4;
+  void* mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return DRTOPK_ENOMEM;
+  uint32_t* buf[2] = {static_cast<uint32_t*>(mem), static_cast<uint32_t*>(mem) + chunk};
+  uint32_t* cv = buf[1] + chunk;  // chunk top-k values / positions
+  uint32_t* ci = cv + kk;
+  uint32_t* rv = ci + kk;  // running list
+  uint32_t* ri = rv + kk;
+  uint32_t* kv = ri + kk;  // candidates (2k)
+  uint32_t* ki = kv + 2 * kk;
+  uint32_t* sv = ki + 2 * kk;  // selection over the candidates
+  uint32_t* si = sv + kk;
+  hipStream_t cs = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+  for (int b = 0; b < 2 && ok; ++b)
+    ok = hipEventCreateWithFlags(&copied[b], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&used[b], hipEventDisableTiming) == hipSuccess;
+  uint32_t r = 0;  // running list length
+  const char* src = static_cast<const char*>(host_keys);
+  for (uint64_t c = 0; c < nchunks && ok; ++c) {
+    const int b = (int)(c & 1);
+    const uint64_t off = c * chunk;
+    const uint64_t len = n - off < chunk ? n - off : chunk;
+    const uint32_t kc = (uint64_t)k < len ? k : (uint32_t)len;
+    // the buffer's previous chunk must be done with before it is overwritten
+    if (c >= 2) ok = hipStreamWaitEvent(cs, used[b], 0) == hipSuccess;
+    ok = ok && hipMemcpyAsync(buf[b], src + off * 4, len * 4, hipMemcpyHostToDevice, cs) == hipSuccess;
+    ok = ok && hipEventRecord(copied[b], cs) == hipSuccess;
+    ok = ok && hipStreamWaitEvent(s, copied[b], 0) == hipSuccess;
+    if (!ok) break;
+    if (r == 0) {
+      st = topk_select(buf[b], len, kc, dtype, rv, ri, stream);
+      r = kc;
+    } else {
+      st = topk_select(buf[b], len, kc, dtype, cv, ci, stream);
+      if (st == DRTOPK_OK) {
+        hipLaunchKernelGGL(k_stream_concat, dim3(grid_for(r + kc, 256, 1024)), dim3(256), 0, s, rv, ri, r, cv, ci, kc,
+                           off, kv, ki);
+        const uint32_t m = r + kc < k ? r + kc : k;
+        st = topk_select(kv, r + kc, m, dtype, sv, si, stream);
+        if (st == DRTOPK_OK)
+          hipLaunchKernelGGL(k_stream_gather, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, sv, si, m, ki, rv, ri);
+        r = m;
+      }
+    }
+    // positions of the first chunk need no offset: it starts at 0
+    if (st != DRTOPK_OK) break;
+    ok = hipEventRecord(used[b], s) == hipSuccess;
+  }
+  if (ok && st == DRTOPK_OK) {
+    ok = hipMemcpyAsync(out_vals, rv, kk * 4, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    if (ok && out_idx) ok = hipMemcpyAsync(out_idx, ri, kk * 4, hipMemcpyDeviceToDevice, s) == hipSuccess;
+  }
+  // everything below uses the buffers: wait for both streams before freeing
+  if (cs) (void)hipStreamSynchronize(cs);
+  (void)hipStreamSynchronize(s);
+  for (int b = 0; b < 2; ++b) {
+    if (copied[b]) (void)hipEventDestroy(copied[b]);
+    if (used[b]) (void)hipEventDestroy(used[b]);
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  (void)hipFree(mem);
+  if (st != DRTOPK_OK) return st;
+  return ok && hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
 }
 
 const char* drtopk_status_string(int status) {

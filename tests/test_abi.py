@@ -74,6 +74,17 @@ def test_dtype_codes_without_gpu():
     assert drt.footprint(1 << 24, 1000, "f32-min") == drt.footprint(1 << 24, 1000, "f32")
 
 
+def test_host_stream_arguments_without_gpu():
+    L = drt.lib()
+    host = (ctypes.c_uint32 * 16)()
+    out = ctypes.c_void_p(32)
+    assert L.topk_select_host(None, 16, 1, 0, 0, out, None, None) == 1  # no input
+    assert L.topk_select_host(host, 16, 1, 0, 0, None, None, None) == 1  # no output
+    assert L.topk_select_host(host, 16, 17, 0, 0, out, None, None) == 1  # k > n
+    assert L.topk_select_host(host, 16, 1, 0, 17, out, None, None) == 1  # chunk > n
+    assert L.topk_select_host(host, 16, 1, 3, 0, out, None, None) == 1  # not a key type
+
+
 def test_null_pointers_rejected():
     L = drt.lib()
     assert L.topk_select(None, 10, 1, 0, ctypes.c_void_p(32), None, None) == 1
