@@ -26,7 +26,7 @@ its timed region:
            queries/s and p50/p99 latency (arrival -> completion on the host).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-adversarial] [--no-batched] [--no-serving] [--no-smallest] [--no-by-k]
+                       [--no-adversarial] [--no-batched] [--no-serving] [--no-smallest] [--no-by-k] [--no-host]
                        [--copy-calibration]
        python bench.py --delegate-vector A:B[,A:B...]
                        (profiling aid: only the delegate vector of the 2^30 uniform input for
@@ -180,6 +180,32 @@ def bench_shard(drt, torch, t_u, t_f):
     return out
 
 
+def bench_host_stream(drt, synth, torch):
+    """Keys in host memory (N = 2^30 uint32 uniform), streamed through the device in
+    chunks of 2^26 keys by topk_select_host: pageable (numpy) and pinned (a torch
+    tensor allocated with pin_memory=True) host buffers, k = 1024 and 131072.  The
+    rate is bound by the host-to-device copy, not the kernels."""
+    import numpy as np
+    print("[bench] host stream: 2^30 keys in host memory", file=sys.stderr, flush=True)
+    x = synth.uniform_u32(N, synth.DEFAULT_SEED)
+    pinned = torch.empty(N, dtype=torch.int32, pin_memory=True)
+    pinned.numpy().view(np.uint32)[:] = x
+    out = []
+    for name, arr in (("pageable", x), ("pinned", pinned.numpy().view(np.uint32))):
+        for k in (1024, 131072):
+            drt.topk_select_host(arr, k, chunk=1 << 26)  # warm-up
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                drt.topk_select_host(arr, k, chunk=1 << 26)
+                ts.append(time.perf_counter() - t0)
+            best = min(ts)
+            out.append({"memory": name, "k": k, "ms_min": best * 1e3, "ms_median": sorted(ts)[1] * 1e3,
+                        "keys_per_s": N / best, "GBps": 4 * N / best / 1e9})
+    del x, pinned
+    return out
+
+
 def bench_delegates_vs_plain(drt, torch, t_u):
     """The paper's claim that delegates speed up the radix top-k they wrap: at
     N = 2^28 uint32 uniform, the delegate method (planner's alpha, beta) against
@@ -274,6 +300,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adversarial", action="store_true")
     ap.add_argument("--no-smallest", action="store_true", help="skip the k smallest / int32 cases")
+    ap.add_argument("--no-host", action="store_true", help="skip top-k of keys in host memory")
     ap.add_argument("--no-by-k", action="store_true",
                     help="skip delegates against the plain radix select and the 2^27 shard cases")
     ap.add_argument("--delegate-vector", default=None, metavar="A:B,...",
@@ -425,6 +452,7 @@ def main() -> int:
     adversarial = None if args.no_adversarial else bench_adversarial(drt, torch, args)
     batched = None if args.no_batched else bench_batched(drt, synth, torch, args)
     serving = None if args.no_serving else bench_serving(drt, synth, torch, np)
+    host_stream = None if args.no_host else bench_host_stream(drt, synth, torch)
 
     out = {
         "metric": METRIC,
@@ -454,6 +482,7 @@ def main() -> int:
         "smallest_and_i32": smallest_i32,
         "delegates_vs_plain_radix": by_k,
         "shard_2p27": shard,
+        "host_stream": host_stream,
         "adversarial": adversarial,
         "batched": batched,
         "serving": serving,
