@@ -150,8 +150,8 @@ struct TailSmem {
     uint64_t sortbuf[kSmallCap];  // 64 KiB: the one-block LDS sorts
     struct {
       uint32_t hist[kBins];
-      Stage<1024> sq;
-      Stage<4096> sc;
+      Stage<8 * kTailThreads> sq;   // a whole Q claim's queued subranges
+      Stage<16 * kTailThreads> sc;  // a whole Q claim's delegates at beta <= 2
     } st;
   } u;
   uint32_t scan[kTailThreads];
@@ -756,9 +756,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             mr.add(take, comp(kk[j], ii[j]));
             stage_push(sm.u.st.sc, take, kk[j], ii[j]);
           }
-          stage_flush2_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, kTailThreads, sm.u.st.sc, &ctl->nc, ctl->cap_c,
-                           a.ckey, a.cidx, kTailThreads * BETA, ctl);
         }
+        // the stages hold a whole claim: one capacity check per claim
+        stage_flush2_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, 8 * kTailThreads, sm.u.st.sc, &ctl->nc,
+                         ctl->cap_c, a.ckey, a.cidx, 8 * kTailThreads * BETA, ctl);
       }
       sub = 0;
     }
