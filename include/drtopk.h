@@ -267,6 +267,17 @@ int drtopk_server_replay(drtopk_server_t* server, const drtopk_problem_t* reqs, 
  * DRTOPK_ENOMEM and later submits return DRTOPK_ENOMEM. */
 int drtopk_server_destroy(drtopk_server_t* server);
 
+/* Top-k of keys that carry a payload (key-value pairs; the paper's own
+ * selections run on (key, value) pairs, Section 5.1): as topk_select, plus
+ * out_payload[r] = payload[out_idx[r]] for every output slot r.
+ *   payload      device, n elements of payload_bytes (4 or 8) each
+ *   out_payload  device, k elements of payload_bytes
+ *   out_idx      may be NULL (the positions are then kept in the workspace)
+ * Errors as topk_select; DRTOPK_EINVAL for another payload_bytes or a null
+ * payload / out_payload. */
+int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, const void* payload,
+                        int payload_bytes, void* out_vals, uint32_t* out_idx, void* out_payload, void* stream);
+
 /* Top-k over keys in HOST memory, streamed through the device in chunks: for
  * inputs larger than the device memory (the paper's reload of sub-vectors
  * that do not fit one GPU, Section 5.4).  Each chunk's top-k (positions

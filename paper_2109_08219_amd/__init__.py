@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
             "drtopk_footprint": [u64, u32, i32, ctypes.POINTER(u64)],
             "drtopk_read_probe": [vp, u64, vp, vp],
             "topk_select_host": [vp, u64, u32, i32, u64, vp, vp, vp],
+            "topk_select_payload": [vp, u64, u32, i32, vp, i32, vp, vp, vp, vp],
             "drtopk_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "drtopk_server_submit": [vp, ctypes.POINTER(Problem), ctypes.POINTER(u64)],
             "drtopk_server_wait": [vp, u64, ctypes.POINTER(ctypes.c_double)],
@@ -439,6 +440,27 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def topk_select_payload(keys, payload, k: int, *, dtype=None, largest: bool = True, stream=None):
+    """Top-k of keys (as topk_select) and the payload of each selected key:
+    payload is a device tensor of n 4- or 8-byte elements.  Returns (values,
+    indices, payloads)."""
+    torch = _torch()
+    code = _prep(keys, dtype, largest)
+    if not payload.is_cuda or payload.dim() != 1 or not payload.is_contiguous() or payload.numel() != keys.numel():
+        raise ValueError("payload must be a contiguous 1-D device tensor with one element per key")
+    if payload.element_size() not in (4, 8):
+        raise ValueError("payload elements must be 4 or 8 bytes")
+    out_vals = torch.empty(k, dtype=keys.dtype, device=keys.device)
+    out_idx = torch.empty(k, dtype=torch.int32, device=keys.device)
+    out_pay = torch.empty(k, dtype=payload.dtype, device=keys.device)
+    rc = lib().topk_select_payload(ctypes.c_void_p(keys.data_ptr()), keys.numel(), k, code,
+                                   ctypes.c_void_p(payload.data_ptr()), payload.element_size(),
+                                   ctypes.c_void_p(out_vals.data_ptr()), ctypes.c_void_p(out_idx.data_ptr()),
+                                   ctypes.c_void_p(out_pay.data_ptr()), _stream(stream))
+    _check(rc, "topk_select_payload")
+    return out_vals, out_idx, out_pay
 
 
 def topk_select_host(keys, k: int, *, chunk: int = 0, largest: bool = True, dtype=None, stream=None):

@@ -500,6 +500,12 @@ __global__ void k_stream_concat(const uint32_t* rv, const uint32_t* ri, uint32_t
     }
   }
 }
+// Payload of each output slot: out[r] = payload[idx[r]] (T = 4- or 8-byte element).
+template <typename T>
+__global__ void k_gather_payload(const T* payload, const uint32_t* idx, uint32_t k, T* out) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) out[i] = payload[idx[i]];
+}
+
 // New running list: the selected candidates' values and whole-input positions.
 __global__ void k_stream_gather(const uint32_t* sv, const uint32_t* si, uint32_t m, const uint32_t* ki,
                                 uint32_t* rv, uint32_t* ri) {
@@ -819,6 +825,34 @@ int drtopk_read_probe(const void* keys, uint64_t n, uint32_t* out_max, void* str
   hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(64), 0, s, out_max);
   hipLaunchKernelGGL(k_read_probe, dim3(g), dim3(256), 0, s, static_cast<const uint32_t*>(keys), n, chunk, out_max);
   return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+}
+
+int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, const void* payload,
+                        int payload_bytes, void* out_vals, uint32_t* out_idx, void* out_payload, void* stream) {
+  if (!payload || !out_payload || (payload_bytes != 4 && payload_bytes != 8)) return DRTOPK_EINVAL;
+  int st = check_args(keys, n, k, dtype);
+  if (st) return st;
+  if (!out_vals) return DRTOPK_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint32_t* idx = out_idx;
+  void* tmp = nullptr;
+  if (!idx) {  // positions are needed for the gather
+    if (hipMallocAsync(&tmp, (size_t)k * 4, s) != hipSuccess) return DRTOPK_ENOMEM;
+    idx = static_cast<uint32_t*>(tmp);
+  }
+  st = topk_select(keys, n, k, dtype, out_vals, idx, stream);
+  if (st == DRTOPK_OK) {
+    const unsigned g = grid_for(k, 256, 1024);
+    if (payload_bytes == 4)
+      hipLaunchKernelGGL(k_gather_payload<uint32_t>, dim3(g), dim3(256), 0, s, static_cast<const uint32_t*>(payload),
+                         idx, k, static_cast<uint32_t*>(out_payload));
+    else
+      hipLaunchKernelGGL(k_gather_payload<uint64_t>, dim3(g), dim3(256), 0, s, static_cast<const uint64_t*>(payload),
+                         idx, k, static_cast<uint64_t*>(out_payload));
+    if (hipGetLastError() != hipSuccess) st = DRTOPK_EDEVICE;
+  }
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  return st;
 }
 
 int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, uint64_t chunk, void* out_vals,

@@ -74,6 +74,17 @@ def test_dtype_codes_without_gpu():
     assert drt.footprint(1 << 24, 1000, "f32-min") == drt.footprint(1 << 24, 1000, "f32")
 
 
+def test_payload_arguments_without_gpu():
+    L = drt.lib()
+    d = ctypes.c_void_p(16)
+    out = ctypes.c_void_p(32)
+    assert L.topk_select_payload(d, 100, 5, 0, None, 4, out, None, out, None) == 1  # no payload
+    assert L.topk_select_payload(d, 100, 5, 0, d, 2, out, None, out, None) == 1  # 2-byte payload
+    assert L.topk_select_payload(d, 100, 5, 0, d, 8, out, None, None, None) == 1  # no payload output
+    assert L.topk_select_payload(d, 100, 101, 0, d, 8, out, None, out, None) == 1  # k > n
+    assert L.topk_select_payload(d, 100, 5, 0, d, 8, None, None, out, None) == 1  # no value output
+
+
 def test_host_stream_arguments_without_gpu():
     L = drt.lib()
     host = (ctypes.c_uint32 * 16)()
