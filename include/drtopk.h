@@ -28,7 +28,10 @@
  * pointer, k == 0, k > n, n >= 2^32, unknown dtype), DRTOPK_ENOMEM when the
  * workspace cannot be allocated (nothing is launched), DRTOPK_EDEVICE when a
  * launch or device query fails.  Faults inside kernels surface at the next
- * synchronisation as HIP errors.
+ * synchronisation as HIP errors.  The kernels also run internal consistency
+ * checks (a failure means a library defect, never bad input); a failed check
+ * is recorded per (device, stream) and reported by drtopk_check, by the
+ * calls that synchronise (stats, topk_select_host) and by the server.
  */
 #ifndef DRTOPK_H
 #define DRTOPK_H
@@ -226,8 +229,10 @@ int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes);
  * Results are bit-identical to topk_select / kth_select on each request
  * alone.  plain = 1 turns the server into the per-request baseline: one
  * topk_select (or kth_select) call per request, in arrival order.
+ * A launch whose kernels raise an internal check flag (see drtopk_check)
+ * completes all of its requests with DRTOPK_EDEVICE.
  * The device is the caller's current device at creation.  A server keeps a
- * record (about 100 bytes) of every request it has served until destroyed. */
+ * record (about 100 bytes) of every request until a drain reports it. */
 typedef struct drtopk_server drtopk_server_t;
 typedef struct {
   uint64_t hbm_budget; /* bytes; 0 = 8 GiB */
@@ -247,10 +252,12 @@ int drtopk_server_create(const drtopk_server_config_t* cfg, drtopk_server_t** ou
 /* Queues one request (arrival = now); *ticket identifies it. */
 int drtopk_server_submit(drtopk_server_t* server, const drtopk_problem_t* req, uint64_t* ticket);
 /* Blocks until the request completes; returns its status and, if non-NULL,
- * its latency in microseconds. */
+ * its latency in microseconds.  DRTOPK_EINVAL for a ticket never issued or
+ * already reported by a drain. */
 int drtopk_server_wait(drtopk_server_t* server, uint64_t ticket, double* latency_us);
-/* Blocks until every submitted request has completed; returns the first
- * failure status among requests completed since the previous drain, else OK. */
+/* Blocks until every submitted request has completed; returns a failure
+ * status among the requests completed since the previous drain, else OK, and
+ * drops their records (their tickets are no longer valid for wait). */
 int drtopk_server_drain(drtopk_server_t* server);
 /* Latency percentiles (nearest rank) over requests completed since the last
  * reset; reset != 0 starts a new window. */
@@ -272,7 +279,8 @@ int drtopk_server_destroy(drtopk_server_t* server);
  * out_payload[r] = payload[out_idx[r]] for every output slot r.
  *   payload      device, n elements of payload_bytes (4 or 8) each
  *   out_payload  device, k elements of payload_bytes
- *   out_idx      may be NULL (the positions are then kept in the workspace)
+ *   out_idx      may be NULL (the positions are then kept in the stream's
+ *                workspace; no per-call allocation)
  * Errors as topk_select; DRTOPK_EINVAL for another payload_bytes or a null
  * payload / out_payload. */
 int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, const void* payload,
@@ -293,7 +301,8 @@ int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, con
  * returns once the result is complete (it synchronises `stream`), so the
  * host buffer may be reused on return.  DRTOPK_EINVAL on bad arguments,
  * DRTOPK_ENOMEM if the buffers cannot be allocated, DRTOPK_EDEVICE if a copy
- * or launch fails. */
+ * or launch fails or the stream's check record holds flags at the end (they
+ * stay recorded for drtopk_check). */
 int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, uint64_t chunk, void* out_vals,
                      uint32_t* out_idx, void* stream);
 
@@ -307,6 +316,36 @@ int drtopk_read_probe(const void* keys, uint64_t n, uint32_t* out_max, void* str
 
 /* Frees the calling thread's current device's workspaces (synchronises it). */
 int drtopk_release_workspace(void);
+
+/* Internal check flags (bits of *flags):
+ *   1   a radix-select bucket search found no bucket holding the sought rank
+ *   2   fewer survivors than k reached the output step
+ *   16  a bounded buffer was full and writes past its end were dropped
+ *   64  a phase wait inside a kernel gave up after about one second
+ *   128 an output sort group exceeded one workgroup
+ * Any of them means the outputs of the calls concerned are not to be trusted. */
+enum {
+  DRTOPK_CHECK_SELECT = 1,
+  DRTOPK_CHECK_FEW = 2,
+  DRTOPK_CHECK_CAPACITY = 16,
+  DRTOPK_CHECK_WAIT = 64,
+  DRTOPK_CHECK_GROUP = 128
+};
+
+/* Synchronises `stream`, then reports and clears the check flags recorded by
+ * the kernels of every call enqueued on it (on the current device) since the
+ * previous drtopk_check of that stream: DRTOPK_OK and *flags = 0 if none,
+ * DRTOPK_EDEVICE with the OR of the flags otherwise (flags may be NULL).
+ * DRTOPK_EDEVICE with *flags = 0 if the synchronisation itself fails. */
+int drtopk_check(void* stream, uint32_t* flags);
+
+/* Testing hook for the error path: caps the survivor buffers of the delegate
+ * method (topk_select, kth_select, and the single-problem part of the other
+ * entry points) at `cap` entries for calls planned after it; 0 restores the
+ * planner's bound.  With a cap below what an input needs, kernels drop the
+ * writes past it, raise flag 16 (and usually 2) and exit normally.
+ * Process-wide; not for production use. */
+int drtopk_set_survivor_cap(uint64_t cap);
 
 /* Human-readable name of a status code (static string). */
 const char* drtopk_status_string(int status);

@@ -26,10 +26,18 @@ _DTYPES = {"u32": U32, "f32": F32, "i32": I32}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported"}
 
 
+CHECK_FLAGS = {1: "select", 2: "few survivors", 16: "capacity", 64: "wait timeout", 128: "sort group"}
+
+
 class DrTopkError(RuntimeError):
-    def __init__(self, status: int, what: str):
-        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status})")
+    def __init__(self, status: int, what: str, flags: int = 0):
+        extra = ""
+        if flags:
+            names = ", ".join(v for b, v in CHECK_FLAGS.items() if flags & b)
+            extra = f"; device check flags {flags:#x} ({names})"
+        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status}){extra}")
         self.status = status
+        self.flags = flags
 
 
 class Options(ctypes.Structure):
@@ -107,6 +115,8 @@ def lib() -> ctypes.CDLL:
             "drtopk_server_replay": [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_double), u32,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
             "drtopk_server_destroy": [vp],
+            "drtopk_check": [vp, ctypes.POINTER(u32)],
+            "drtopk_set_survivor_cap": [u64],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -174,13 +184,31 @@ def _opts(alpha, beta, mode, variant=0):
                    variant)
 
 
+def check_stream(stream=None) -> None:
+    """Synchronises the stream and raises DrTopkError (with .flags) if a kernel of any call
+    enqueued on it since the previous check failed an internal consistency check."""
+    f = ctypes.c_uint32(0)
+    rc = lib().drtopk_check(_stream(stream), ctypes.byref(f))
+    if rc != 0:
+        raise DrTopkError(rc, "drtopk_check", f.value)
+
+
+check = check_stream
+
+
+def set_survivor_cap(cap: int) -> None:
+    """Testing hook: caps the delegate method's survivor buffers (0 = planner's bound)."""
+    _check(lib().drtopk_set_survivor_cap(int(cap)), "drtopk_set_survivor_cap")
+
+
 def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, largest: bool = True, alpha=None,
-                beta=None, mode=None, variant: int = 0, stats: bool = False, stream=None):
+                beta=None, mode=None, variant: int = 0, stats: bool = False, check: bool = False, stream=None):
     """The k largest keys, sorted descending (ties: lower position first), and their positions;
     largest=False: the k smallest, sorted ascending (ties: lower position first).
 
     Returns (values, indices[, Stats]).  values has the keys' dtype; indices are int64-free uint32
-    positions stored in a torch.int32 tensor (bit pattern of the uint32 position)."""
+    positions stored in a torch.int32 tensor (bit pattern of the uint32 position).  check=True
+    synchronises the stream afterwards and raises if a device check failed (see check())."""
     torch = _torch()
     code = _prep(keys, dtype, largest)
     if out_vals is None:
@@ -194,13 +222,16 @@ def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, larges
                               ctypes.byref(opts) if opts is not None else None,
                               ctypes.byref(st) if st is not None else None, _stream(stream))
     if rc != 0 and st is not None and st.err_flags:
-        raise DrTopkError(rc, f"topk_select (device check flags {st.err_flags:#x})")
+        raise DrTopkError(rc, "topk_select", st.err_flags)
     _check(rc, "topk_select")
+    if check:
+        check_stream(stream)
     return (out_vals, out_idx, st) if stats else (out_vals, out_idx)
 
 
-def kth_select(keys, k: int, out=None, *, dtype=None, largest: bool = True, stream=None):
-    """The k-th largest key (largest=False: k-th smallest), counting multiplicity, as a 1-element tensor."""
+def kth_select(keys, k: int, out=None, *, dtype=None, largest: bool = True, check: bool = False, stream=None):
+    """The k-th largest key (largest=False: k-th smallest), counting multiplicity, as a 1-element tensor.
+    check=True: synchronise and raise on a failed device check."""
     torch = _torch()
     code = _prep(keys, dtype, largest)
     if out is None:
@@ -208,6 +239,8 @@ def kth_select(keys, k: int, out=None, *, dtype=None, largest: bool = True, stre
     rc = lib().kth_select(ctypes.c_void_p(keys.data_ptr()), keys.numel(), k, code,
                           ctypes.c_void_p(out.data_ptr()), _stream(stream))
     _check(rc, "kth_select")
+    if check:
+        check_stream(stream)
     return out
 
 
@@ -253,9 +286,11 @@ class Batch:
                                      vb + 4 * self.off[i] if vb else None,
                                      ib + 4 * self.off[i] if ib else None, kb + 4 * i)
 
-    def run(self, stream=None) -> None:
+    def run(self, stream=None, check: bool = False) -> None:
         rc = lib().topk_select_batched(self._descs, self.count, _stream(stream))
         _check(rc, "topk_select_batched")
+        if check:
+            check_stream(stream)
 
     def _as_keys(self, t, i):
         return t.view(self.keys[i].dtype)
@@ -270,17 +305,17 @@ class Batch:
         return self._as_keys(self.kth[i:i + 1], i)
 
 
-def topk_select_batched(problems, *, stream=None):
+def topk_select_batched(problems, *, check: bool = False, stream=None):
     """problems as for Batch.  Returns a list of (values, indices, kth)."""
     b = Batch(problems)
-    b.run(stream)
+    b.run(stream, check)
     return [(b.values(i), b.indices(i), b.kth_value(i)) for i in range(b.count)]
 
 
-def kth_select_batched(problems, *, stream=None):
+def kth_select_batched(problems, *, check: bool = False, stream=None):
     """problems as for topk_select_batched.  Returns a list of 1-element k-th value tensors."""
     b = Batch(problems, kth_only=True)
-    b.run(stream)
+    b.run(stream, check)
     return [b.kth_value(i) for i in range(b.count)]
 
 

@@ -271,7 +271,7 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
 // LDS, they are compacted, sorted and the first k written: two passes over
 // the keys for typical inputs, at most seven for massive ties.
 template <bool VEC>
-__device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
+__device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm, uint32_t* rec) {
   const Codec cx = codec_of(d.dtype);
   const uint32_t n = (uint32_t)d.n, k = d.k, n4 = vec_end<VEC>(n);
   const Keys<VEC> ks(d.keys, n4);
@@ -338,6 +338,8 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm) {
     }
   __syncthreads();
   const uint32_t ns = sm.nsurv < kBSurv ? sm.nsurv : kBSurv;
+  // the class chosen last fits by construction (a single member after the last digit)
+  if (threadIdx.x == 0 && sm.nsurv > kBSurv) record_err(rec, ERR_CAP);
   b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
 }
 
@@ -526,10 +528,11 @@ __device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
 // vector and finishes the problem (radix select over the keys if its
 // survivors overflow).  Nobody waits for anybody.
 template <bool VEC>
-__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm);
+__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
+                              uint32_t* rec);
 
 template <bool VEC>
-__device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
+__device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm, uint32_t* rec) {
   if (d.n <= kBSmallN) {
     b_small<VEC>(d, sm);
     return;
@@ -539,11 +542,12 @@ __device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm) {
     if (S <= kBMaxS && S > d.k && b_delegate<VEC>(d, sm)) return;
     __syncthreads();
   }
-  b_radix<VEC>(d, sm);
+  b_radix<VEC>(d, sm, rec);
 }
 
 template <bool VEC>
-__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
+__device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
+                              uint32_t* rec) {
   const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const uint32_t tlog = alpha > kBTileLog ? alpha : kBTileLog;
   const uint32_t lo = tile << tlog;
@@ -567,19 +571,20 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   __syncthreads();
   if (b_finish<VEC>(d, sm)) return;
   __syncthreads();
-  b_radix<VEC>(d, sm);
+  b_radix<VEC>(d, sm, rec);
 }
 
-__device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm) {
+__device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm, uint32_t* rec) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (vec) b_problem_v<true>(d, sm);
-  else b_problem_v<false>(d, sm);
+  if (vec) b_problem_v<true>(d, sm, rec);
+  else b_problem_v<false>(d, sm, rec);
 }
 
-__device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm) {
+__device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
+                                  uint32_t* rec) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (vec) b_tile<true>(d, tile, arrive, Dg, sm);
-  else b_tile<false>(d, tile, arrive, Dg, sm);
+  if (vec) b_tile<true>(d, tile, arrive, Dg, sm, rec);
+  else b_tile<false>(d, tile, arrive, Dg, sm, rec);
 }
 
 // Work items (problem << 8 | tile), claimed from *counter (starts at 0):
@@ -589,7 +594,7 @@ __device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* a
 // Any grid size works: no workgroup waits for another.
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(
     const BatchDesc* __restrict__ descs, const uint32_t* __restrict__ items, uint32_t nitems, uint32_t* counter,
-    uint32_t* arrive, uint64_t* Dg) {
+    uint32_t* arrive, uint64_t* Dg, uint32_t* rec) {
   __shared__ BatchSmem sm;
   for (;;) {
     __syncthreads();
@@ -601,8 +606,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint32_t it = items[w];
     const uint32_t i = it >> 8;
     const BatchDesc d = descs[i];
-    if (d.tiles > 1) b_tile_any(d, it & 0xFFu, &arrive[i], Dg, sm);
-    else b_problem(d, sm);
+    if (d.tiles > 1) b_tile_any(d, it & 0xFFu, &arrive[i], Dg, sm, rec);
+    else b_problem(d, sm, rec);
   }
 }
 
@@ -612,15 +617,15 @@ constexpr uint32_t kBInline = 32;
 struct BatchInline {
   BatchDesc d[kBInline];
 };
-__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched_inline(BatchInline b) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batched_inline(BatchInline b, uint32_t* rec) {
   __shared__ BatchSmem sm;
-  b_problem(b.d[blockIdx.x], sm);
+  b_problem(b.d[blockIdx.x], sm, rec);
 }
 
 // One problem, descriptor by value: the single-problem path for small inputs.
-__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_one(BatchDesc d) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_one(BatchDesc d, uint32_t* rec) {
   __shared__ BatchSmem sm;
-  b_problem(d, sm);
+  b_problem(d, sm, rec);
 }
 
 }  // namespace drtopk

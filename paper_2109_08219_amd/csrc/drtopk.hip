@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -67,6 +68,10 @@ int default_beta(uint64_t n, uint32_t k) {
 
 bool valid_beta(int b) { return b == 1 || b == 2 || b == 4 || b == 8; }
 
+// Testing hook: survivor-buffer capacity of the delegate method (0 = the
+// planner's bound).  A smaller cap makes the kernels drop writes and flag it.
+std::atomic<uint64_t> g_cap_override{0};
+
 int floor_log2(uint64_t x) { return 63 - __builtin_clzll(x); }
 
 // Autotuner table: measured (alpha, beta) per (form, floor log2 n, floor log2 k).
@@ -92,7 +97,8 @@ bool batched_eligible(uint64_t n, uint32_t k);
 // than across the device: one launch, no workspace.
 constexpr uint64_t kOneWgMaxN = 1ull << 16;
 
-int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P) {
+int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_options_t* opt, Plan* P,
+              bool pos_in_ws = false) {
   Plan p;
   p.n = n;
   p.k = k;
@@ -139,6 +145,8 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
       const uint64_t c = (m / p.beta) * L + m;
       p.cap_c = c < n ? c : n;
     }
+    const uint64_t cap_hook = g_cap_override.load(std::memory_order_relaxed);
+    if (cap_hook && cap_hook < p.cap_c) p.cap_c = cap_hook;
     // one block per chunk, about 1024 blocks: at n = 2^30 that is 4 MiB
     // chunks (one round of blocks), which stream best for beta = 1; beta > 1
     // needs the parallelism of 1 MiB chunks for its merges.  A chunk holds
@@ -174,6 +182,7 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
       p.off_sidx = seg(p.cap_c * 4);
     }
   }
+  if (pos_in_ws) p.off_pos = seg((size_t)k * 4);
   p.off_okey = seg((size_t)k * 4);
   p.off_oidx = seg((size_t)k * 4);
   if (p.M) {
@@ -200,6 +209,10 @@ struct Workspace {
   size_t bhost_bytes = 0;
   hipEvent_t bev = nullptr;
   bool bev_pending = false;
+  // check record of the calls on this stream: kErrWords words in pinned host
+  // memory, written by kernels whose internal checks fail, read and cleared
+  // by drtopk_check (kept across drtopk_release_workspace)
+  uint32_t* rec = nullptr;
 };
 
 std::mutex g_mu;
@@ -210,6 +223,36 @@ Workspace* workspace_entry(int dev, void* stream) {
   auto& slot = g_ws[{dev, stream}];
   if (!slot) slot.reset(new (std::nothrow) Workspace());
   return slot.get();
+}
+
+// Existing entry of (dev, stream), or null (never creates one).
+Workspace* find_workspace(int dev, void* stream) {
+  std::lock_guard<std::mutex> g(g_mu);
+  auto it = g_ws.find({dev, stream});
+  return it == g_ws.end() ? nullptr : it->second.get();
+}
+
+// Called with ws->mu held: the stream's check record exists (zeroed).
+int ensure_record(Workspace* ws) {
+  if (ws->rec) return DRTOPK_OK;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, kErrWords * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return DRTOPK_ENOMEM;
+  }
+  std::memset(p, 0, kErrWords * sizeof(uint32_t));
+  ws->rec = static_cast<uint32_t*>(p);
+  return DRTOPK_OK;
+}
+
+// Flags held by a check record (bit i <=> word i set); clears it when `reset`.
+uint32_t read_record(volatile uint32_t* rec, bool reset) {
+  uint32_t f = 0;
+  for (int i = 0; i < kErrWords; ++i) {
+    if (rec[i]) f |= 1u << i;
+    if (reset) rec[i] = 0;
+  }
+  return f;
 }
 
 // Called with ws->mu held.
@@ -312,24 +355,31 @@ uint32_t host_dec(int code, uint32_t u) {
   }
 }
 
-// Runs the whole path; `fn` (optional) runs under the workspace lock after the
-// enqueue, with the plan and workspace pointer.
+// Runs the whole path; `after` runs under the workspace lock after the
+// enqueue, with the plan, the workspace pointer and the stream.  pos_in_ws:
+// with out_idx NULL the output positions go to a workspace segment
+// (Plan::off_pos) that `after` may read on the stream.
 template <typename F>
 int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
                void* out_kth, bool kth_only, const drtopk_options_t* opt, void* stream, F&& after,
-               bool filter_only = false) {
+               bool filter_only = false, bool pos_in_ws = false) {
   int st = check_args(keys, n, k, dtype);
   if (st) return st;
   Plan p;
-  st = make_plan(keys, n, k, dtype, opt, &p);
+  const bool ws_pos = pos_in_ws && !out_idx && !kth_only;
+  st = make_plan(keys, n, k, dtype, opt, &p, ws_pos);
   if (st) return st;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
   Workspace* ws = workspace_entry(dev, stream);
   if (!ws) return DRTOPK_ENOMEM;
   std::lock_guard<std::mutex> g(ws->mu);
+  st = ensure_record(ws);
+  if (st) return st;
   st = ensure_bytes(ws, p.total);
   if (st) return st;
+  p.rec = ws->rec;
+  if (ws_pos) out_idx = at<uint32_t>(ws->ptr, p.off_pos);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const uint32_t* kp = static_cast<const uint32_t*>(keys);
   if (p.mode == 3) {
@@ -343,7 +393,7 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
     d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
     d.out_idx = kth_only ? nullptr : out_idx;
     d.out_kth = static_cast<uint32_t*>(out_kth);
-    hipLaunchKernelGGL(k_one, dim3(1), dim3(kBT), 0, s, d);
+    hipLaunchKernelGGL(k_one, dim3(1), dim3(kBT), 0, s, d, p.rec);
     if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
     return after(p, ws->ptr, s);
   }
@@ -426,7 +476,7 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
   if (items.size() <= kBInline && !split) {  // descriptors as kernel arguments
     BatchInline b{};
     for (size_t i = 0; i < items.size(); ++i) b.d[i] = descs[i];
-    hipLaunchKernelGGL(k_batched_inline, dim3((unsigned)items.size()), dim3(kBT), 0, s, b);
+    hipLaunchKernelGGL(k_batched_inline, dim3((unsigned)items.size()), dim3(kBT), 0, s, b, ws->rec);
     return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
   }
   const size_t off_desc = 64;
@@ -456,7 +506,7 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
   hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, s, reinterpret_cast<const BatchDesc*>(dv + off_desc),
                      reinterpret_cast<const uint32_t*>(dv + off_items), (uint32_t)nwork,
                      reinterpret_cast<uint32_t*>(dv), reinterpret_cast<uint32_t*>(dv + off_arrive),
-                     reinterpret_cast<uint64_t*>(dv + off_dg));
+                     reinterpret_cast<uint64_t*>(dv + off_dg), ws->rec);
   if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
   return DRTOPK_OK;
 }
@@ -607,7 +657,9 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
       Workspace* ws = workspace_entry(dev, stream);
       if (!ws) return DRTOPK_ENOMEM;
       std::lock_guard<std::mutex> lock(ws->mu);
-      int st = launch_batched(small, reinterpret_cast<hipStream_t>(stream), ws);
+      int st = ensure_record(ws);
+      if (st) return st;
+      st = launch_batched(small, reinterpret_cast<hipStream_t>(stream), ws);
       if (st) return st;
     }
     for (const drtopk_problem_t* q : large) {
@@ -691,8 +743,11 @@ int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int bet
   Workspace* ws = workspace_entry(dev, stream);
   if (!ws) return DRTOPK_ENOMEM;
   std::lock_guard<std::mutex> lock(ws->mu);
+  st = ensure_record(ws);
+  if (st) return st;
   st = ensure_bytes(ws, p.total);
   if (st) return st;
+  p.rec = ws->rec;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Ctl* ctl = at<Ctl>(ws->ptr, p.off_ctl);
   const uint32_t* kp = static_cast<const uint32_t*>(keys);
@@ -833,26 +888,28 @@ int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, con
   int st = check_args(keys, n, k, dtype);
   if (st) return st;
   if (!out_vals) return DRTOPK_EINVAL;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  uint32_t* idx = out_idx;
-  void* tmp = nullptr;
-  if (!idx) {  // positions are needed for the gather
-    if (hipMallocAsync(&tmp, (size_t)k * 4, s) != hipSuccess) return DRTOPK_ENOMEM;
-    idx = static_cast<uint32_t*>(tmp);
+  try {
+    // the gather is enqueued under the workspace lock, so with out_idx NULL it
+    // reads the positions from the workspace before any later call on the
+    // stream can overwrite them
+    return run_common(keys, n, k, dtype, out_vals, out_idx, nullptr, false, nullptr, stream,
+                      [&](const Plan& p, void* ws, hipStream_t s) {
+                        const uint32_t* idx = out_idx ? out_idx : at<uint32_t>(ws, p.off_pos);
+                        const unsigned g = grid_for(k, 256, 1024);
+                        if (payload_bytes == 4)
+                          hipLaunchKernelGGL(k_gather_payload<uint32_t>, dim3(g), dim3(256), 0, s,
+                                             static_cast<const uint32_t*>(payload), idx, k,
+                                             static_cast<uint32_t*>(out_payload));
+                        else
+                          hipLaunchKernelGGL(k_gather_payload<uint64_t>, dim3(g), dim3(256), 0, s,
+                                             static_cast<const uint64_t*>(payload), idx, k,
+                                             static_cast<uint64_t*>(out_payload));
+                        return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+                      },
+                      false, true);
+  } catch (...) {
+    return DRTOPK_EDEVICE;
   }
-  st = topk_select(keys, n, k, dtype, out_vals, idx, stream);
-  if (st == DRTOPK_OK) {
-    const unsigned g = grid_for(k, 256, 1024);
-    if (payload_bytes == 4)
-      hipLaunchKernelGGL(k_gather_payload<uint32_t>, dim3(g), dim3(256), 0, s, static_cast<const uint32_t*>(payload),
-                         idx, k, static_cast<uint32_t*>(out_payload));
-    else
-      hipLaunchKernelGGL(k_gather_payload<uint64_t>, dim3(g), dim3(256), 0, s, static_cast<const uint64_t*>(payload),
-                         idx, k, static_cast<uint64_t*>(out_payload));
-    if (hipGetLastError() != hipSuccess) st = DRTOPK_EDEVICE;
-  }
-  if (tmp) (void)hipFreeAsync(tmp, s);
-  return st;
 }
 
 int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, uint64_t chunk, void* out_vals,
@@ -930,7 +987,35 @@ int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, u
   if (cs) (void)hipStreamDestroy(cs);
   (void)hipFree(mem);
   if (st != DRTOPK_OK) return st;
-  return ok && hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+  if (!ok || hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
+  // the stream has finished: a failed internal check of its calls is reported
+  // here (and stays recorded for drtopk_check)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  if (Workspace* ws = find_workspace(dev, stream)) {
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (ws->rec && read_record(ws->rec, false)) return DRTOPK_EDEVICE;
+  }
+  return DRTOPK_OK;
+}
+
+int drtopk_check(void* stream, uint32_t* flags) {
+  if (flags) *flags = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return DRTOPK_EDEVICE;
+  uint32_t f = 0;
+  if (Workspace* ws = find_workspace(dev, stream)) {
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (ws->rec) f |= read_record(ws->rec, true);
+  }
+  if (flags) *flags = f;
+  return f ? DRTOPK_EDEVICE : DRTOPK_OK;
+}
+
+int drtopk_set_survivor_cap(uint64_t cap) {
+  g_cap_override.store(cap, std::memory_order_relaxed);
+  return DRTOPK_OK;
 }
 
 const char* drtopk_status_string(int status) {

@@ -90,9 +90,34 @@ struct Ctl {
   uint32_t cap_q; // capacity of the qualifying-subrange list
   uint32_t cap_c; // capacity of the survivor buffer
   uint32_t all;   // 1: fewer delegates than k, every subrange qualifies (t = lowest)
+  uint32_t* rec;  // the stream's sticky check record (kErrWords words, not cleared per call)
   uint32_t boff[kBins + 1];   // first output slot of each bucket
   uint32_t gfirst[kBins + 1]; // first bucket of each sort group
 };
+
+// Internal consistency checks.  A failed check means a defect of the library
+// (or the survivor-capacity testing hook), never bad input; the flags are
+// OR-ed into Ctl::err for this call's statistics and recorded in the stream's
+// check record, which stays set until the host reads and clears it.
+enum : uint32_t {
+  ERR_SELECT = 1u,  // a radix-select bucket search found no bucket holding the rank
+  ERR_FEW = 2u,     // fewer survivors than k reached the output step
+  ERR_CAP = 16u,    // a bounded buffer was full: writes past its end were dropped
+  ERR_WAIT = 64u,   // a phase wait gave up after about a second
+  ERR_GROUP = 128u, // an output sort group exceeded one workgroup
+};
+constexpr int kErrWords = 8;  // check record: word i set <=> flag bit i raised
+
+// Records `bit` (one of the ERR_ flags) in the record `rec`: word log2(bit)
+// is set by a plain store, so concurrent setters of different flags never
+// overwrite each other, and no atomic to host memory is needed.
+__device__ __forceinline__ void record_err(uint32_t* rec, uint32_t bit) {
+  if (rec) rec[__builtin_ctz(bit)] = 1u;
+}
+__device__ __forceinline__ void flag_err(Ctl* c, uint32_t bit) {
+  atomicOr(&c->err, bit);
+  record_err(c->rec, bit);
+}
 
 // Fill levels clamped to their buffers (a violated bound sets err instead of
 // writing past the end).

@@ -143,7 +143,7 @@ __device__ inline void finish_pass(uint32_t* gh, uint32_t* ticket, Sel* sel, int
     sel->mask = mask | (dm << sh);
     sel->rank = s_out[1];
     sel->found = s_out[2];
-    if (!s_out[2]) ctl->err |= 1u;
+    if (!s_out[2]) flag_err(ctl, ERR_SELECT);
   }
 }
 
@@ -198,7 +198,7 @@ __device__ __forceinline__ void stage_flush(Stage<CAP>& S, uint32_t* gcount, uin
       gkey[base + i] = S.key[i];
       if (gidx) gidx[base + i] = S.idx[i];
     } else {
-      ctl->err |= 16u;
+      flag_err(ctl, ERR_CAP);
     }
   }
   __syncthreads();
@@ -266,7 +266,7 @@ __device__ inline void finish_delegates(const uint32_t* lh, Ctl* ctl, uint32_t k
   const uint32_t c1 = f1 ? atomic_load_u32(&ctl->histL[b1]) : 0xFFFFFFFFu;
   if (threadIdx.x == 0) {
     const uint64_t w0 = (uint64_t)(kD - r0) + c0, w1 = (uint64_t)(kD - r1) + c1;
-    if (!f0 && !f1) ctl->err |= 1u;
+    if (!f0 && !f1) flag_err(ctl, ERR_SELECT);
     const bool use_log = f1 && (!f0 || w1 < w0);
     ctl->wmap = use_log ? 1u : 0u;
     ctl->wbin = use_log ? b1 : b0;
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(1024) void k_final_small(const uint32_t* __restrict
   if (gated_off(ctl, gate)) return;
   const uint64_t count = (SRC == SRC_C) ? (uint64_t)clamp_nc(ctl) : count_static;
   if (count > (uint64_t)kSmallCap || count < k) {
-    if (threadIdx.x == 0) ctl->err |= 2u;
+    if (threadIdx.x == 0) flag_err(ctl, ERR_FEW);
     return;
   }
   uint32_t P = 64;
@@ -805,7 +805,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ A, u
   }
 }
 
-static __global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t all) {
+static __global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t all, uint32_t* rec) {
   uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
   const uint32_t nw = offsetof(Ctl, cap_q) / 4;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) w[i] = 0;
@@ -813,6 +813,7 @@ static __global__ void k_init(Ctl* ctl, uint32_t cap_q, uint32_t cap_c, uint32_t
     ctl->cap_q = cap_q;
     ctl->cap_c = cap_c;
     ctl->all = all;
+    ctl->rec = rec;
   }
 }
 

@@ -115,7 +115,7 @@ struct Runner {
                         uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st, PhaseMarks& pm) {
     Ctl* ctl = at<Ctl>(ws, p.off_ctl);
     hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, st, ctl, (uint32_t)p.S, (uint32_t)p.cap_c,
-                       p.all ? 1u : 0u);
+                       p.all ? 1u : 0u, p.rec);
     pm.start(st);
     uint32_t* okey = at<uint32_t>(ws, p.off_okey);
     uint32_t* oidx = at<uint32_t>(ws, p.off_oidx);
@@ -242,7 +242,7 @@ void run_codec(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals
 
 template <int DT>
 void delegates_codec(const Plan& p, const uint32_t* keys, uint32_t* dkey, uint32_t* didx, Ctl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, st, ctl, (uint32_t)p.S, (uint32_t)p.cap_c, 0u);
+  hipLaunchKernelGGL(k_init, dim3(8), dim3(1024), 0, st, ctl, (uint32_t)p.S, (uint32_t)p.cap_c, 0u, p.rec);
   Runner<DT>::delegate(p, keys, dkey, didx, ctl, st);
   if constexpr (DT != DT_U32)
     hipLaunchKernelGGL((k_decode_inplace<DT>), dim3(grid_for(p.nd, 256 * 4, 4096)), dim3(256), 0, st, dkey, p.nd);

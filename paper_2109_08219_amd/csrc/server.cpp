@@ -4,7 +4,9 @@
 // Clients submit requests (device pointers, as for topk_select_batched) from
 // any thread.  One dispatcher thread per server:
 //   * completes launches whose event has fired (latency = completion seen on
-//     the host - arrival), releasing their HBM footprint;
+//     the host - arrival), releasing their HBM footprint; a launch whose
+//     kernels raised an internal check flag (drtopk_check on its stream)
+//     fails all of its requests with DRTOPK_EDEVICE;
 //   * when a launch stream is free, takes the oldest queued request: one too
 //     large for a workgroup (n > 2^22 or k > 2048) runs alone through the
 //     single-problem path; otherwise the queued small requests are admitted in
@@ -63,8 +65,8 @@ struct drtopk_server {
   int device = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Req> reqs;        // every request of the server's life, indexed by ticket
-  uint64_t drained = 0;        // requests before this ticket were reported by a drain
+  std::deque<Req> reqs;        // requests not yet reported by a drain: ticket base + i is reqs[i]
+  uint64_t base = 0;           // ticket of reqs.front(); earlier tickets were reported by a drain
   std::deque<uint64_t> qsmall, qlarge;  // submitted, not yet admitted, in arrival order
   std::vector<Slot> slots;
   uint64_t inflight_bytes = 0, max_inflight_bytes = 0;
@@ -74,7 +76,7 @@ struct drtopk_server {
   bool broken = false;      // the dispatcher failed (out of host memory): requests fail
   std::thread th;
 
-  Req& at(uint64_t t) { return reqs[t]; }
+  Req& at(uint64_t t) { return reqs[t - base]; }
   bool queued() const { return !qsmall.empty() || !qlarge.empty(); }
   void loop();
   void run();
@@ -122,11 +124,15 @@ bool drtopk_server::complete_ready() {
       continue;
     }
     const Clock::time_point now = Clock::now();
+    // the launch has finished: a failed internal check of any of its kernels
+    // fails every request of the launch
+    uint32_t flags = 0;
+    const bool flagged = q == hipSuccess && drtopk_check(sl.stream, &flags) != DRTOPK_OK;
     std::lock_guard<std::mutex> g(mu);
     for (uint64_t t : sl.items) {
       Req& r = at(t);
       r.latency_us = us_between(r.arrival, now);
-      if (q != hipSuccess && r.status == DRTOPK_OK) r.status = DRTOPK_EDEVICE;
+      if ((q != hipSuccess || flagged) && r.status == DRTOPK_OK) r.status = DRTOPK_EDEVICE;
       r.done = true;
       lat.push_back(r.latency_us);
     }
@@ -287,7 +293,7 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
     if (s->broken) return DRTOPK_ENOMEM;
     try {
       s->reqs.push_back(r);
-      *ticket = s->reqs.size() - 1;
+      *ticket = s->base + s->reqs.size() - 1;
       (r.large ? s->qlarge : s->qsmall).push_back(*ticket);
     } catch (...) {
       return DRTOPK_ENOMEM;
@@ -308,7 +314,7 @@ int drtopk_server_submit(drtopk_server_t* s, const drtopk_problem_t* req, uint64
 int drtopk_server_wait(drtopk_server_t* s, uint64_t ticket, double* latency_us) {
   if (!s) return DRTOPK_EINVAL;
   std::unique_lock<std::mutex> g(s->mu);
-  if (ticket >= s->reqs.size()) return DRTOPK_EINVAL;
+  if (ticket < s->base || ticket >= s->base + s->reqs.size()) return DRTOPK_EINVAL;
   s->cv_done.wait(g, [&] { return s->at(ticket).done; });
   const Req& r = s->at(ticket);
   if (latency_us) *latency_us = r.latency_us;
@@ -324,10 +330,12 @@ int drtopk_server_drain(drtopk_server_t* s) {
       if (sl.busy) return false;
     return true;
   });
+  // nothing is queued or in flight: every record is complete; report and drop them
   int st = DRTOPK_OK;
-  for (uint64_t t = s->drained; t < s->reqs.size(); ++t)
-    if (s->reqs[t].status != DRTOPK_OK) st = s->reqs[t].status;
-  s->drained = s->reqs.size();
+  for (const Req& r : s->reqs)
+    if (r.status != DRTOPK_OK) st = r.status;
+  s->base += s->reqs.size();
+  s->reqs.clear();
   return st;
 }
 

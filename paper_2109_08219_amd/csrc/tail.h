@@ -118,7 +118,7 @@ __device__ __forceinline__ void stage_flush_coh(Stage<CAP>& S, uint32_t* gcount,
       st_coh(&gkey[base + i], S.key[i]);
       if (gidx) st_coh(&gidx[base + i], S.idx[i]);
     } else {
-      ctl->err |= 16u;
+      flag_err(ctl, ERR_CAP);
     }
   }
   __syncthreads();
@@ -206,7 +206,7 @@ __device__ __forceinline__ void wait_ready(Phase* ph, Ctl* ctl) {
     while (ld_coh(&ph->ready) == 0u) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) {
-        atomicOr(&ctl->err, 64u);
+        flag_err(ctl, ERR_WAIT);
         break;
       }
     }
@@ -234,7 +234,7 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
   uint32_t r = rank;
   const uint32_t nchunks = (count + kSelChunk - 1) / kSelChunk;
   if (nchunks == 0 || rank == 0 || rank > count) {  // inconsistent input: flag, never wait
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->err |= 1u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_err(ctl, ERR_SELECT);
     return 0;
   }
   for (int p = 0; p < kPasses; ++p) {
@@ -272,7 +272,7 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
     if (report(&ph[p], mine, nchunks, sm)) {
       tail_bucket(hist[p], r, sm.scan, sm.out);
       if (threadIdx.x == 0) {
-        if (!sm.out[2]) ctl->err |= 1u;
+        if (!sm.out[2]) flag_err(ctl, ERR_SELECT);
         pub64(pubsel, prefix | ((uint64_t)sm.out[0] << sh));
         st_coh(pubsel + 2, sm.out[1]);
       }
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   // ---- F: the output ---------------------------------------------------------
   const uint32_t nc = ld_coh(&ctl->nc) < ctl->cap_c ? ld_coh(&ctl->nc) : ctl->cap_c;
   if (nc < a.k) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->err |= 2u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_err(ctl, ERR_FEW);
     return;
   }
   if (nc <= (uint32_t)kSmallCap) {
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
               st_coh(&a.skey[slot], kk[j]);
               st_coh(&a.sidx[slot], ii[j]);
             } else {
-              ctl->err |= 16u;
+              flag_err(ctl, ERR_CAP);
             }
           }
         }
@@ -1050,7 +1050,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         if (lo >= a.k || hi <= lo) continue;
         const uint32_t cnt = hi - lo;
         if (cnt > (uint32_t)kSmallCap) {
-          if (threadIdx.x == 0) ctl->err |= 128u;
+          if (threadIdx.x == 0) flag_err(ctl, ERR_GROUP);
           continue;
         }
         sort_and_write<DT>(a.skey + lo, a.sidx + lo, cnt, lo, a.k - lo < cnt ? a.k - lo : cnt, a.k,

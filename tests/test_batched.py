@@ -45,8 +45,7 @@ def run_batch(hosts, *, kth_only=False, offsets=None):
         t = dev(np.concatenate([np.zeros(off, dtype=x.dtype), x]))[off:] if off else dev(x)
         tensors.append((t, k))
     b = drt.Batch(tensors, kth_only=kth_only)
-    b.run()
-    torch.cuda.synchronize()
+    b.run(check=True)
     return b
 
 
@@ -218,8 +217,7 @@ def test_split_problems():
     say("split problems", len(allh))
     b = run_batch(allh)
     check_batch(allh, b, "split")
-    b.run()  # second launch on the same descriptors
-    torch.cuda.synchronize()
+    b.run(check=True)  # second launch on the same descriptors
     check_batch(allh, b, "split repeat")
     say("split, unaligned + k only")
     b = run_batch(hosts, offsets=[1 + (i % 3) for i in range(len(hosts))])

@@ -31,8 +31,8 @@ def dev(x: np.ndarray):
 
 
 def run_topk(x, k, **kw):
-    # stats=True synchronises and raises if a kernel flagged an internal inconsistency
-    vals, idx = drt.topk_select(dev(x), k, stats=True, **kw)[:2]
+    # stats=True and check=True synchronise and raise if a kernel flagged an internal inconsistency
+    vals, idx = drt.topk_select(dev(x), k, stats=True, check=True, **kw)[:2]
     torch.cuda.synchronize()
     return to_np(vals), to_np(idx)
 
@@ -262,11 +262,25 @@ def _full_case(x, dt, ks):
     full = oracle.rank_key(x, dt)
     for k in ks:
         say("full size", dt, "k", k)
-        vals, idx, st = drt.topk_select(t, k, stats=True)
+        vals, idx, st = drt.topk_select(t, k, stats=True, check=True)
         say("  alpha", st.alpha, "beta", st.beta, "scanned", st.scanned, "candidates", st.candidates)
         check_invariants_fast(x, full, k, dt, to_np(vals), to_np(idx))
+        say("full size kth_select", dt, "k", k)
+        check_kth_fast(x, full, k, drt.kth_select(t, k, check=True), to_np(vals))
     del t
     torch.cuda.empty_cache()
+
+
+def check_kth_fast(x, full, k, got, vals=None):
+    """kth_select's value is the k-th largest: fewer than k keys rank above it and at
+    least k at or above it (rank keys from the oracle's order); it is bit-identical to
+    slot k-1 of the (invariant-checked) top-k output when one is given."""
+    g = to_np(got).reshape(-1)[:1].view(x.dtype)
+    kv = oracle.rank_key(g, "f32" if x.dtype == np.float32 else "u32")[0]
+    greater = int(np.count_nonzero(full > kv))
+    assert greater < k <= greater + int(np.count_nonzero(full == kv)), (k, greater)
+    if vals is not None:
+        assert g.view(np.uint32)[0] == vals.view(np.uint32)[k - 1]
 
 
 def check_invariants_fast(x, full, k, dt, vals, idx):
@@ -297,17 +311,22 @@ def test_full_size_adversarial():
     full = oracle.rank_key(x, "f32")
     for beta in (1, 2, 4, 8):
         say("sorted 2^29 k=16384 beta", beta)
-        vals, idx, st = drt.topk_select(t, 16384, beta=beta, stats=True)
+        vals, idx, st = drt.topk_select(t, 16384, beta=beta, stats=True, check=True)
         say("  alpha", st.alpha, "scanned", st.scanned, "candidates", st.candidates)
         check_invariants_fast(x, full, 16384, "f32", to_np(vals), to_np(idx))
+    say("sorted 2^29 kth_select k=16384 and k=1")
+    check_kth_fast(x, full, 16384, drt.kth_select(t, 16384, check=True), to_np(vals))
+    check_kth_fast(x, full, 1, drt.kth_select(t, 1, check=True))
     del t, x, full
     h = synth.heavy_dup_u32(1 << 29, synth.DEFAULT_SEED)
     th = dev(h)
     fullh = oracle.rank_key(h, "u32")
     say("heavy-dup 2^29 k=16384")
-    vals, idx, st = drt.topk_select(th, 16384, stats=True)
+    vals, idx, st = drt.topk_select(th, 16384, stats=True, check=True)
     say("  alpha", st.alpha, "beta", st.beta, "scanned", st.scanned, "candidates", st.candidates)
     check_invariants_fast(h, fullh, 16384, "u32", to_np(vals), to_np(idx))
+    say("heavy-dup 2^29 kth_select k=16384")
+    check_kth_fast(h, fullh, 16384, drt.kth_select(th, 16384, check=True), to_np(vals))
     # closed form: the lowest 16384 positions holding 15
     assert (to_np(idx).view(np.uint32) == np.flatnonzero(h == 15)[:16384]).all()
 

@@ -51,6 +51,6 @@ def test_random_sweep(part):
     for kind, n, k, largest, opts, s in draw_cases(150, 777 + part):
         x, dt = synth.keys(kind, n, s)
         say(kind, "n", n, "k", k, "largest" if largest else "smallest", opts)
-        vals, idx = drt.topk_select(torch.from_numpy(x).cuda(), k, largest=largest, stats=True, **opts)[:2]
+        vals, idx = drt.topk_select(torch.from_numpy(x).cuda(), k, largest=largest, stats=True, check=True, **opts)[:2]
         torch.cuda.synchronize()
         check_exact(x, k, dt, to_np(vals), to_np(idx), f"{kind} n={n} k={k} {opts}", largest=largest)

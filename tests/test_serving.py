@@ -117,3 +117,39 @@ def test_submit_wait_kth_only(reqs):
     assert all(l > 0 for l in lats)
     for i in range(b.count):
         assert to_np(b.kth_value(i)).view(np.uint32)[0] == ref[i][2], i
+
+
+@pytest.fixture(scope="module")
+def full_range():
+    """The serving workload at its full size range: n log-uniform in [2^12, 2^26],
+    uint32 uniform or float32 normal (a fair coin), k log-uniform in [1, 4096].
+    Host copies are kept only for the requests checked against the oracle."""
+    count, seed = 520, 4242
+    hosts, tensors = {}, []
+    for i, (kind, n, k) in enumerate(synth.serving_workload(count, seed, hi_exp=26)):
+        x, dt = synth.keys(kind, n, synth.derive_seed(seed, 9000 + i))
+        if i % 25 == 0:
+            hosts[i] = (x, dt, k)
+        tensors.append((torch.from_numpy(x).cuda(), k))
+    say("full-range requests", count, "largest n", max(t.numel() for t, _ in tensors),
+        "single-path requests", sum(1 for t, k in tensors if t.numel() > (1 << 22) or k > 2048))
+    return hosts, tensors, alone(tensors)
+
+
+@pytest.mark.parametrize("streams,max_batch", [(4, 64), (8, 256)])
+def test_full_range_alone_equals_mix(full_range, streams, max_batch):
+    hosts, tensors, ref = full_range
+    b = drt.Batch(tensors)
+    arr = synth.poisson_arrivals(len(tensors), 30000.0, 19)
+    say("full-range serving mix", streams, max_batch)
+    with drt.Server(streams=streams, max_batch=max_batch) as srv:
+        lat, el = srv.replay(b, arr)
+        st = srv.stats()
+        srv.drain()
+    torch.cuda.synchronize()
+    say("  launches", st.launches, "items", st.launched_items, "p50", round(st.p50_us, 1), "p99", round(st.p99_us, 1))
+    assert st.completed == len(tensors) and st.launched_items == len(tensors)
+    assert_same(b, ref, f"full-range mix {streams} {max_batch}")
+    for i, (x, dt, k) in hosts.items():
+        say("  oracle check of request", i, "n", x.shape[0], "k", k)
+        check_exact(x, k, dt, to_np(b.values(i)), to_np(b.indices(i)), f"full-range serving #{i}")

@@ -45,7 +45,7 @@ def test_sizes_and_k(kind, largest):
         t = dev(x)
         for k in sorted({k for k in (1, 2, 33, 1024, 8193, 20000, n) if k <= n}):
             say(kind, "largest" if largest else "smallest", "n", n, "k", k)
-            vals, idx = drt.topk_select(t, k, largest=largest, stats=True)[:2]
+            vals, idx = drt.topk_select(t, k, largest=largest, stats=True, check=True)[:2]
             kth = drt.kth_select(t, k, largest=largest)
             torch.cuda.synchronize()
             check_exact(x, k, dt, to_np(vals), to_np(idx), f"{kind} n={n} k={k}", largest=largest)
@@ -62,7 +62,7 @@ def test_alpha_beta_invariance_smallest(kind):
         for alpha in (0, 3, 8, 10, 12):
             for beta in (1, 2, 4, 8):
                 say(kind, "smallest k", k, "alpha", alpha, "beta", beta)
-                vals, idx = drt.topk_select(t, k, largest=False, alpha=alpha, beta=beta, mode=1, stats=True)[:2]
+                vals, idx = drt.topk_select(t, k, largest=False, alpha=alpha, beta=beta, mode=1, stats=True, check=True)[:2]
                 torch.cuda.synchronize()
                 assert (to_np(idx).view(np.uint32) == want[1]).all(), (kind, k, alpha, beta)
                 assert (to_np(vals).view(np.uint32) == np.asarray(want[0]).view(np.uint32)).all()
@@ -76,7 +76,7 @@ def test_float_specials_smallest():
     x = pats[rng.integers(0, pats.shape[0], size=100003)].view(np.float32)
     for k in (1, 7, 5000, 100003):
         say("float specials smallest", k)
-        vals, idx = drt.topk_select(dev(x), k, largest=False, stats=True)[:2]
+        vals, idx = drt.topk_select(dev(x), k, largest=False, stats=True, check=True)[:2]
         torch.cuda.synchronize()
         check_exact(x, k, "f32", to_np(vals), to_np(idx), f"specials k={k}", largest=False)
 
@@ -137,7 +137,7 @@ def test_large_smallest(kind, ks):
     t = dev(x)
     for k in ks:
         say("large smallest", kind, "k", k)
-        vals, idx, st = drt.topk_select(t, k, largest=False, stats=True)
+        vals, idx, st = drt.topk_select(t, k, largest=False, stats=True, check=True)
         say("  alpha", st.alpha, "beta", st.beta, "scanned", st.scanned, "candidates", st.candidates)
         check_invariants(x, k, dt, to_np(vals), to_np(idx), f"{kind} 2^28 k={k}", largest=False)
     del t
