@@ -31,6 +31,9 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --delegate-vector A:B[,A:B...]
                        (profiling aid: only the delegate vector of the 2^30 uniform input for
                        each (alpha, beta), twice each, then exit; no JSON line)
+       python bench.py --only adversarial|batched|serving|small
+                       (profiling aid: that part alone, printed as {"section": ..., "result": ...};
+                       not the benchmark line)
 """
 from __future__ import annotations
 
@@ -48,7 +51,7 @@ METRIC = "top-k keys/s and HBM GB/s at N=2^30; batched queries/s + p99 latency"
 HBM_PEAK_GBS = 8000.0
 N = 1 << 30
 KS = (1, 1024, 131072)
-CPU_SAMPLE = 1 << 26
+CPU_K = 1024
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delegate_pass_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08219_amd", "csrc", f) for f in ("kernels.h", "internal.h")]
@@ -307,6 +310,8 @@ def main() -> int:
                     help="only build the delegate vector for these (alpha, beta) pairs (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, whose HBM counters calibrate the traffic figure")
+    ap.add_argument("--only", choices=("adversarial", "batched", "serving", "small"), default=None,
+                    help="run one part alone (for profiler runs); prints that part's result, not the bench line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -322,6 +327,13 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        part = {"adversarial": lambda: bench_adversarial(drt, torch, args),
+                "batched": lambda: bench_batched(drt, synth, torch, args),
+                "serving": lambda: bench_serving(drt, synth, torch, np),
+                "small": lambda: bench_small(drt, synth, torch, args)}[args.only]()
+        print(json.dumps({"section": args.only, "result": part}), flush=True)
+        return 0
     if args.delegate_vector:
         x_u = synth.uniform_u32(N, synth.DEFAULT_SEED)
         t_u = torch.from_numpy(x_u).to(dev)
@@ -334,13 +346,10 @@ def main() -> int:
             print(f"[bench] delegate vector alpha {a} beta {b} done", file=sys.stderr, flush=True)
         return 0
     print(f"[bench] generating 2 x 2^30 keys", file=sys.stderr, flush=True)
-    x_u = synth.uniform_u32(N, synth.DEFAULT_SEED)
+    x_u = synth.uniform_u32(N, synth.DEFAULT_SEED)  # kept: the CPU baseline reads the same host bytes
     t_u = torch.from_numpy(x_u).to(dev)
-    sample_u = x_u[:CPU_SAMPLE].copy()
-    del x_u
     x_f = synth.normal_f32(N, synth.DEFAULT_SEED)
     t_f = torch.from_numpy(x_f).to(dev)
-    sample_f = x_f[:CPU_SAMPLE].copy()
     del x_f
     if args.copy_calibration:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
@@ -431,15 +440,22 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        t_cpu = 0.0
-        for s, dt in ((sample_u, "u32"), (sample_f, "f32")):
-            for k in KS:
-                a = time.perf_counter()
-                oracle.topk_reference(s, k, dt)
-                t_cpu += time.perf_counter() - a
-        cpu = {"value": 6 * CPU_SAMPLE / t_cpu, "unit": "keys/s", "cores": 1, "kind": "oracle",
-               "sample": f"the first 2^26 keys of each input, the same six (dtype, k) calls; "
-                         f"numpy selection oracle (single-threaded partition + sort), {t_cpu:.1f} s"}
+        print("[bench] CPU oracle on the 2^30 uint32 input, k = 1024", file=sys.stderr, flush=True)
+        threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or (os.cpu_count() or 1)
+        a = time.perf_counter()
+        oracle.topk_threaded(x_u, CPU_K, "u32", threads=threads)
+        t_thr = time.perf_counter() - a
+        a = time.perf_counter()
+        oracle.topk_reference(x_u, CPU_K, "u32")
+        t_one = time.perf_counter() - a
+        cpu = {"value": N / t_thr, "unit": "keys/s", "cores": threads, "kind": "oracle",
+               "sample": f"the step's N = 2^30 uint32 input (the same host bytes the GPU reads), k = {CPU_K}: "
+                         f"the oracle's selection split over {threads} threads then merged, {t_thr:.1f} s",
+               "single_thread": {"value": N / t_one, "unit": "keys/s", "cores": 1,
+                                 "sample": f"same input and k, the oracle's selection route on one thread, "
+                                           f"{t_one:.1f} s"},
+               "host_cpu_count": os.cpu_count()}
+    del x_u
 
     case_rows = [{k: v for k, v in c.items() if k not in ("keys", "vals", "idx")} for c in cases]
     del cases

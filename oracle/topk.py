@@ -21,6 +21,8 @@ bit patterns at ``indices``.
 from __future__ import annotations
 
 import heapq
+import os
+import threading
 
 import numpy as np
 
@@ -110,6 +112,47 @@ def topk_heap(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     kept = sorted(heap, reverse=True)
     idx = np.array([-m for _, m in kept], dtype=np.int64)
     return np.asarray(values)[idx], idx
+
+
+def topk_threaded(values: np.ndarray, k: int, dtype: str, largest: bool = True, threads: int | None = None):
+    """The selection route on every host core: split, select per part, merge.
+
+    Positions [0, n) are cut into ``threads`` contiguous parts (default: the
+    OMP_NUM_THREADS share, else every core); a thread takes its part's
+    min(k, part) highest-ranked positions by ``topk_select``.  Every member of
+    the answer is among its own part's top k (fewer than k elements rank above
+    it anywhere, so also inside its part), so the answer is the first k of the
+    union of the part lists in the (key desc, position asc) order.  numpy's
+    selection and sorting release the interpreter lock, so the parts run in
+    parallel.
+    """
+    n = _check(values, k)
+    values = np.asarray(values)
+    T = threads or int(os.environ.get("OMP_NUM_THREADS") or 0) or os.cpu_count() or 1
+    T = max(1, min(int(T), n))
+    bounds = [n * i // T for i in range(T + 1)]
+    parts: list = [None] * T
+    errors: list = []
+
+    def work(i: int) -> None:
+        try:
+            lo, hi = bounds[i], bounds[i + 1]
+            _, idx = topk_select(values[lo:hi], min(k, hi - lo), dtype, largest)
+            parts[i] = idx + lo
+        except BaseException as e:  # re-raised in the caller
+            errors.append(e)
+
+    pool = [threading.Thread(target=work, args=(i,)) for i in range(T)]
+    for t in pool:
+        t.start()
+    for t in pool:
+        t.join()
+    if errors:
+        raise errors[0]
+    cand = np.concatenate(parts)
+    key = _key(values[cand], dtype, largest)
+    idx = cand[np.lexsort((cand, -key))[:k]].astype(np.int64)
+    return values[idx], idx
 
 
 def topk(values: np.ndarray, k: int, dtype: str, largest: bool = True):

@@ -63,13 +63,24 @@ struct BatchSmem {
   uint32_t out[4];
 };
 
-__device__ __forceinline__ uint64_t wave_max64(uint64_t m) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t y = shfl_xor64(m, o);
-    m = y > m ? y : m;
-  }
+template <int M>
+__device__ __forceinline__ uint64_t max_cross(uint64_t m) {
+  const uint64_t y = lane_cross64<M>(m);
+  return y > m ? y : m;
+}
+// Maximum over each block of G consecutive lanes (G a wave-uniform power of
+// two, at most 64), held by all of its lanes; VALU lane operations only.
+__device__ __forceinline__ uint64_t group_max64(uint64_t m, uint32_t G) {
+  if (G > 1) m = max_cross<1>(m);
+  if (G > 2) m = max_cross<2>(m);
+  if (G > 4) m = max_cross<4>(m);
+  if (G > 8) m = max_cross<8>(m);
+  if (G > 16) m = max_cross<16>(m);
+  if (G > 32) m = max_cross<32>(m);
   return m;
+}
+__device__ __forceinline__ uint64_t wave_max64(uint64_t m) {
+  return max_cross<32>(max_cross<16>(max_cross<8>(max_cross<4>(max_cross<2>(max_cross<1>(m))))));
 }
 
 // The keys of one problem behind a raw buffer resource: loads are plain
@@ -425,10 +436,7 @@ __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint
         const uint64_t x = comp(cx.enc(v[j][c]), p + c);
         if (p + c < n4 && x > m) m = x;
       }
-      for (uint32_t o = 1; o < G; o <<= 1) {
-        const uint64_t y = shfl_xor64(m, (int)o);
-        m = y > m ? y : m;
-      }
+      m = group_max64(m, G);
       if ((lane & (G - 1)) == 0 && p < n4) atomicMax((unsigned long long*)&sm.D[p >> alpha], (unsigned long long)m);
     }
   }

@@ -69,8 +69,7 @@ struct Ctl {
   uint32_t cut_lo, cut_hi;  // key interval of the cut bin
   uint32_t cut_rank;        // rank of the kD-th delegate inside the cut bin
   uint32_t cut_count;       // delegates in the cut bin
-  uint64_t cmax;            // largest survivor composite
-  uint64_t ncmin;           // complement of the smallest survivor composite (so zero is neutral)
+  uint32_t bstar;           // output bucket holding slot k-1 (buckets after it are not scattered)
   uint32_t bigbucket;       // an output bucket overflows one workgroup: take the select path
   uint32_t ngroups;         // output sort groups
   uint32_t need_merge;      // the large-k merge-sort kernels must run (select fallback taken)
@@ -82,7 +81,7 @@ struct Ctl {
   uint32_t uniq_idx;  // position of a unique entry found by a tail pass
   uint32_t tpub[2];   // threshold t published by block 0 of the tail (coherent stores)
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
-  uint64_t max1;  // largest delegate composite (k = 1 is answered by the delegate pass)
+  uint64_t max1;  // largest delegate composite = largest element (the k = 1 answer)
   uint32_t nq;    // subranges to re-read
   uint32_t nc;    // survivors
   uint32_t nout;  // compacted outputs (large-survivor path)
@@ -206,6 +205,34 @@ __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// The value held by a lane in the other M-half of this lane's 2M-lane block
+// (M a power of two below 64), by VALU lane operations only: DPP quad
+// permutes (M = 1, 2), DPP row half-mirror and mirror (4, 8: lane i of an
+// 8- or 16-lane row pairs with 7 - i or 15 - i), and the gfx950 row and half
+// swaps (16, 32).  Exact lane ^ M for M = 1, 2, 16, 32; for 4 and 8 it is
+// another lane of the other half, which is what a butterfly reduction needs
+// once the lanes of each M-block agree (their results then equal lane ^ M's).
+template <int M>
+__device__ __forceinline__ uint32_t lane_cross32(uint32_t v) {
+  if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (M == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+  else if constexpr (M == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+  else if constexpr (M == 16) {
+    // both results hold this lane's own value and its partner's (one each)
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return r[0] == v ? r[1] : r[0];
+  } else {
+    static_assert(M == 32, "lane_cross32: M in {1, 2, 4, 8, 16, 32}");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return r[0] == v ? r[1] : r[0];
+  }
+}
+template <int M>
+__device__ __forceinline__ uint64_t lane_cross64(uint64_t v) {
+  return ((uint64_t)lane_cross32<M>((uint32_t)(v >> 32)) << 32) | lane_cross32<M>((uint32_t)v);
 }
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {

@@ -42,13 +42,16 @@ struct TopB {
       c[0] = g[0] ? x : c[0];
     }
   }
-  // Replace this list by the top-BETA of (this list, the list of lane ^ m).
-  // Max of one list against the other reversed is bitonic and holds the top
-  // BETA; half-cleaners then sort it.
-  __device__ __forceinline__ void merge_xor(int m) {
+  // Replace this list by the top-BETA of (this list, the list of a lane in
+  // the other M-half of this lane's 2M-block); after the step both lanes hold
+  // the same list, so steps M = 1, 2, 4, ... leave every lane of each block
+  // with the block's top-BETA.  Max of one list against the other reversed is
+  // bitonic and holds the top BETA; half-cleaners then sort it.
+  template <int M>
+  __device__ __forceinline__ void merge() {
     uint64_t o[BETA];
 #pragma unroll
-    for (int j = 0; j < BETA; ++j) o[j] = shfl_xor64(c[j], m);
+    for (int j = 0; j < BETA; ++j) o[j] = lane_cross64<M>(c[j]);
 #pragma unroll
     for (int j = 0; j < BETA; ++j) c[j] = c[j] > o[BETA - 1 - j] ? c[j] : o[BETA - 1 - j];
 #pragma unroll
@@ -64,6 +67,18 @@ struct TopB {
     }
   }
 };
+
+// Top-BETA of every block of G consecutive lanes (G a wave-uniform power of
+// two, at most 64), held by all of its lanes.
+template <int BETA>
+__device__ __forceinline__ void merge_lanes(TopB<BETA>& tb, uint32_t G) {
+  if (G > 1) tb.template merge<1>();
+  if (G > 2) tb.template merge<2>();
+  if (G > 4) tb.template merge<4>();
+  if (G > 8) tb.template merge<8>();
+  if (G > 16) tb.template merge<16>();
+  if (G > 32) tb.template merge<32>();
+}
 
 // ---------------------------------------------------------------------------
 // block helpers (blockDim.x == 256)
@@ -245,13 +260,15 @@ struct DirectOut {
 // the bin holding the kD-th largest delegate, and keeps the map whose cut
 // leaves the smaller set W (all delegates in that bin or above).
 __device__ inline void finish_delegates(const uint32_t* lh, Ctl* ctl, uint32_t kD, uint32_t* s_scan,
-                                        uint32_t* s_out, int* s_last, const uint64_t* bmax, bool direct) {
+                                        uint32_t* s_out, int* s_last, const uint64_t* bmax) {
   for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
     const uint32_t a = lh[i], b = lh[kBins + i];
     if (a) atomicAdd(&ctl->histD[0][i], a);
     if (b) atomicAdd(&ctl->histL[i], b);
   }
-  if (direct && threadIdx.x == 0 && *bmax) atomicMax((unsigned long long*)&ctl->max1, (unsigned long long)*bmax);
+  // the largest delegate is the largest element: the k = 1 answer, and the top
+  // of the survivors' bucket map in the tail
+  if (threadIdx.x == 0 && *bmax) atomicMax((unsigned long long*)&ctl->max1, (unsigned long long)*bmax);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) *s_last = (atomicAdd(&ctl->ticketD[0], 1u) == gridDim.x - 1) ? 1 : 0;
@@ -338,8 +355,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
         for (int c = 0; c < 4; ++c)
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
         if (((j + 1) & wps_mask) == 0) {
-#pragma unroll
-          for (int m = 1; m < 64; m <<= 1) tb.merge_xor(m);
+          merge_lanes<BETA>(tb, 64);
           if (lane == 0 && sb < n) emit_delegates<BETA>(sb >> alpha, tb, dkey, didx, lh, bmax);
           tb.clear();
         }
@@ -418,7 +434,7 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
         }
       }
     }
-    for (uint32_t m = 1; m < G; m <<= 1) tb.merge_xor((int)m);
+    merge_lanes<BETA>(tb, G);
     if (l == 0) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
   }
 }
@@ -456,7 +472,7 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
-        for (uint32_t m = 1; m < gl; m <<= 1) tb.merge_xor((int)m);
+        merge_lanes<BETA>(tb, gl);
         if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh, bmax);
       }
     }
@@ -499,7 +515,7 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
     delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax, out.on != 0);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax);
   if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 
@@ -527,7 +543,7 @@ __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restr
     emit_delegates<BETA>(s, tb, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax, out.on != 0);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax);
   if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 

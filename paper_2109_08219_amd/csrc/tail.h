@@ -538,48 +538,46 @@ __device__ inline void sort_and_write(const uint32_t* key, const uint32_t* idx, 
     sort_and_write_e<DT, 16>(key, idx, count, first_slot, limit, k, out_vals, out_idx, out_kth, lds);
 }
 
-// Running max / min of survivor composites (they size the output buckets):
-// per thread in registers while a phase runs (MMReg), merged when the block
-// leaves the phase -- a wave reduction, one LDS atomic per wave (MinMax) and
-// one device atomic per block.  Per-survivor LDS atomics on two addresses
-// serialise within each wave: at n = 2^30, k = 131072 (beta = 2, about 131 k
-// delegates taken directly) they held the Q phase at 34 us against 24 us now.
-struct MinMax {
-  unsigned long long mx, nmn;
+// Output buckets of the survivors.  Every survivor ranks at or above the
+// threshold T and at or below the largest element, so the map is fixed as
+// soon as T is: bucket(x) = 2047 - (top 11 significant bits of x - T over
+// the range up to the largest element), bucket 0 holding the largest.  Q and
+// S count the survivors they write into it (LDS, flushed per block before
+// the block reports its chunks), so no pass over the survivors is needed to
+// find the bucket that holds output slot k-1.
+struct BucketMap {
+  uint64_t lo;
+  uint32_t sh;
+  __device__ __forceinline__ uint32_t operator()(uint64_t x) const { return 2047u - (uint32_t)((x - lo) >> sh); }
 };
-struct MMReg {
-  uint64_t mx = 0, nmn = 0;  // largest composite, complement of the smallest
-  __device__ __forceinline__ void add(bool pred, uint64_t c) {
-    const uint64_t x = pred ? c : 0ull, y = pred ? ~c : 0ull;
-    mx = x > mx ? x : mx;
-    nmn = y > nmn ? y : nmn;
+
+// Whole wave active: every lane with `pred` adds one to h[bin].  When all of
+// them share one bin (sorted or tied inputs, where per-lane atomics on one
+// address would serialise) the wave adds its count with a single atomic.
+__device__ __forceinline__ void hist_add_wave(uint32_t* h, bool pred, uint32_t bin) {
+  const uint64_t m = __ballot(pred);
+  if (!m) return;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const uint32_t b0 = (uint32_t)__shfl((int)bin, leader);
+  if (__all(!pred || bin == b0)) {
+    if ((int)lane_id() == leader) atomicAdd(&h[b0], (uint32_t)__popcll(m));
+  } else if (pred) {
+    atomicAdd(&h[bin], 1u);
   }
-};
-__device__ __forceinline__ void mm_init(MinMax& m) {
-  if (threadIdx.x == 0) { m.mx = 0ull; m.nmn = 0ull; }
 }
-// Block-uniform (every lane of every wave): wave-level lane exchanges.
-__device__ __forceinline__ void mm_flush(MinMax& m, MMReg& r, Ctl* ctl) {
-  uint64_t a = r.mx, b = r.nmn;
-#define DRTOPK_MM_STEP(M)                                           \
-  {                                                                 \
-    const uint64_t a_ = lane_xor64<M>(a), b_ = lane_xor64<M>(b);    \
-    a = a_ > a ? a_ : a;                                            \
-    b = b_ > b ? b_ : b;                                            \
-  }
-  DRTOPK_MM_STEP(1) DRTOPK_MM_STEP(2) DRTOPK_MM_STEP(4) DRTOPK_MM_STEP(8) DRTOPK_MM_STEP(16) DRTOPK_MM_STEP(32)
-#undef DRTOPK_MM_STEP
-  if (lane_id() == 0 && a) {
-    atomicMax(&m.mx, (unsigned long long)a);
-    atomicMax(&m.nmn, (unsigned long long)b);
-  }
-  r.mx = 0;
-  r.nmn = 0;
+
+// Adds the block's LDS bucket counts to the global counts and clears them.
+// Block-uniform.
+__device__ __forceinline__ void hist_flush(uint32_t* h, uint32_t* g) {
   __syncthreads();
-  if (threadIdx.x == 0 && m.mx) {
-    atomicMax(reinterpret_cast<unsigned long long*>(&ctl->cmax), m.mx);
-    atomicMax(reinterpret_cast<unsigned long long*>(&ctl->ncmin), m.nmn);
+  for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
+    const uint32_t v = h[i];
+    if (v) {
+      atomicAdd(&g[i], v);
+      h[i] = 0;
+    }
   }
+  __syncthreads();
 }
 
 // One block: sort survivors (<= kSmallCap) and write the first k.
@@ -600,7 +598,7 @@ constexpr uint32_t kGroup = 2048;  // output positions per sort group (a group h
 // every queue lookup first, then every key load, then the tests.
 template <int DT, int STEPS>
 __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, uint64_t total, uint64_t T,
-                                            TailSmem& sm, MMReg& mr, Ctl* ctl) {
+                                            TailSmem& sm, const BucketMap& bm, uint32_t* bh, Ctl* ctl) {
   const uint64_t lmask = (1ull << a.alpha) - 1;
   uint64_t pp[STEPS];
 #pragma unroll
@@ -629,7 +627,7 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
       const uint32_t kk = enc<DT>(vv[jj][c]);
       const uint64_t cc = comp(kk, (uint32_t)pos);
       const bool take = pos < a.n && cc >= T;
-      mr.add(take, cc);
+      hist_add_wave(bh, take, take ? bm(cc) : 0u);
       stage_push(sm.u.st.sc, take, kk, (uint32_t)pos);
     }
     stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
@@ -639,8 +637,6 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
 template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   __shared__ TailSmem sm;
-  __shared__ MinMax mm;
-  MMReg mr;
   Ctl* ctl = a.ctl;
   Phase* ph = ctl->ph;
   if (blockIdx.x == 0) stamp(ctl, kPhases + 1);
@@ -709,12 +705,23 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->selD.prefix = T;  // host statistics
 
+  // survivors' output buckets over [T, largest element]; counted in LDS (the
+  // output sort's bins, free until the output step)
+  BucketMap bm;
+  {
+    const uint64_t top = ld_coh64(&ctl->max1);
+    const uint32_t rb = bitlen64(top > T ? top - T : 0ull);
+    bm.lo = T;
+    bm.sh = rb > 11u ? rb - 11u : 0u;
+  }
+  uint32_t* bh = sm.rbins;
+  for (int i = threadIdx.x; i < kBins; i += kTailThreads) bh[i] = 0;
+
   // ---- Q: Rule 3 against T -----------------------------------------------------
   // Subrange s is re-read iff its beta-th delegate ranks above T; otherwise its
   // delegates ranked >= T are survivors.  (T = 0 when there are fewer real
   // delegates than k: every subrange with beta real delegates is re-read.)
   if (threadIdx.x == 0) { sm.u.st.sq.n = 0; sm.u.st.sc.n = 0; }
-  mm_init(mm);
   {
     constexpr uint32_t kQChunk = kTailThreads * 8;
     const uint32_t nchunks = (uint32_t)((a.S + kQChunk - 1) / kQChunk);
@@ -753,7 +760,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
 #pragma unroll
           for (int j = 0; j < BETA; ++j) {
             const bool take = ok && !scan && ii[j] != kInvalid && comp(kk[j], ii[j]) >= T;
-            mr.add(take, comp(kk[j], ii[j]));
+            hist_add_wave(bh, take, take ? bm(comp(kk[j], ii[j])) : 0u);
             stage_push(sm.u.st.sc, take, kk[j], ii[j]);
           }
         }
@@ -788,7 +795,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
           ii = a.didx[s * BETA + j];
           take = ii != kInvalid && comp(kk, ii) >= T;
         }
-        mr.add(take, comp(kk, ii));
+        hist_add_wave(bh, take, take ? bm(comp(kk, ii)) : 0u);
         stage_push(sm.u.st.sc, take, kk, ii);
       }
       stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
@@ -798,7 +805,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     // a phase's completion then implies all of its output is visible
     stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, true, 0);
     stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, true, 0);
-    mm_flush(mm, mr, ctl);
+    hist_flush(bh, ctl->bcount);
     if (report(&ph[PH_Q], mine, nchunks, sm)) {
       stamp(ctl, PH_Q);
       raise_ready(&ph[PH_Q]);
@@ -820,7 +827,6 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     const uint32_t nchunks = (uint32_t)((total + chunk - 1) / chunk);
     const uint64_t lmask = (1ull << a.alpha) - 1;
     if (threadIdx.x == 0) sm.u.st.sc.n = 0;
-    mm_init(mm);
     uint32_t mine = 0;
     for (;;) {
       const uint32_t ch = claim(&ph[PH_S], nchunks, sm);
@@ -828,10 +834,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       ++mine;
       if (VEC && a.alpha >= 2) {
         const uint64_t first = (uint64_t)ch * chunk;
-        if (steps == 8) s_claim_vec<DT, 8>(a, first, total, T, sm, mr, ctl);
-        else if (steps == 4) s_claim_vec<DT, 4>(a, first, total, T, sm, mr, ctl);
-        else if (steps == 2) s_claim_vec<DT, 2>(a, first, total, T, sm, mr, ctl);
-        else s_claim_vec<DT, 1>(a, first, total, T, sm, mr, ctl);
+        if (steps == 8) s_claim_vec<DT, 8>(a, first, total, T, sm, bm, bh, ctl);
+        else if (steps == 4) s_claim_vec<DT, 4>(a, first, total, T, sm, bm, bh, ctl);
+        else if (steps == 2) s_claim_vec<DT, 2>(a, first, total, T, sm, bm, bh, ctl);
+        else s_claim_vec<DT, 1>(a, first, total, T, sm, bm, bh, ctl);
         continue;
       }
       for (uint32_t j = 0; j < chunk; j += kStep) {
@@ -863,14 +869,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
           const uint32_t kk = enc<DT>(v[c]);
           const uint64_t cc = comp(kk, (uint32_t)pos[c]);
           const bool take = in[c] && cc >= T;
-          mr.add(take, cc);
+          hist_add_wave(bh, take, take ? bm(cc) : 0u);
           stage_push(sm.u.st.sc, take, kk, (uint32_t)pos[c]);
         }
         stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
       }
     }
     stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, true, 0);
-    mm_flush(mm, mr, ctl);
+    hist_flush(bh, ctl->bcount);
     if (report(&ph[PH_S], mine, nchunks, sm)) {
       stamp(ctl, PH_S);
       raise_ready(&ph[PH_S]);
@@ -895,88 +901,92 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     return;
   }
 
-  // Many survivors: bucket them by the top 11 significant bits of
-  // (composite - smallest), highest bucket first, scatter, and sort groups of
-  // buckets (about kGroup output slots each) in LDS.
-  const uint64_t cmax = ld_coh64(&ctl->cmax), cmin = ~ld_coh64(&ctl->ncmin);
-  const uint32_t bsh = bitlen64(cmax - cmin) > 11u ? bitlen64(cmax - cmin) - 11u : 0u;
-  {
-    for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
-    const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
-    uint32_t mine = 0;
-    for (;;) {
-      const uint32_t c = claim(&ph[PH_B1], nchunks, sm);
-      if (c >= nchunks) break;
-      ++mine;
-      for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
-        const uint32_t i = c * kWChunk + j + threadIdx.x;
-        if (i < nc) {
-          const uint64_t x = comp(ld_coh(&a.ckey[i]), ld_coh(&a.cidx[i]));
-          atomicAdd(&sm.u.st.hist[2047u - (uint32_t)((x - cmin) >> bsh)], 1u);
-        }
-      }
+  // Many survivors.  Q and S counted them into output buckets; one block
+  // turns the counts into bucket offsets (exclusive scan, bucket 0 first),
+  // finds the bucket b* holding output slot k-1, and cuts the buckets up to
+  // b* into sort groups: group w holds the buckets whose first slot lies in
+  // [w*kGroup, (w+1)*kGroup), so a group holds < 2 kGroup when no bucket up
+  // to b* exceeds kGroup.  Buckets after b* hold no output and are neither
+  // scattered nor sorted.  An overfull bucket up to b* (massive ties) takes
+  // the select path instead.
+  if (claim(&ph[PH_B1], 1, sm) == 0) {
+    constexpr int PER = kBins / kTailThreads;
+    uint32_t* lb = sm.u.st.hist;
+    const int t0 = threadIdx.x * PER;
+    uint32_t cnt[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      cnt[j] = ld_coh(&ctl->bcount[t0 + j]);
+      sum += cnt[j];
     }
+    sm.scan[threadIdx.x] = sum;
+    if (threadIdx.x == 0) { sm.out[0] = kBins; sm.out[1] = 0; }
     __syncthreads();
-    if (mine)
-      for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
-        const uint32_t v = sm.u.st.hist[i];
-        if (v) atomicAdd(&ctl->bcount[i], v);
-      }
-    if (report(&ph[PH_B1], mine, nchunks, sm)) {
-      // Bucket offsets (exclusive scan, bucket 0 = highest composites) and the
-      // sort groups: group w holds the buckets whose first slot lies in
-      // [w*kGroup, (w+1)*kGroup); gfirst[w] is its first bucket and
-      // gfirst[nwin] marks the end.  Bucket b opens every window after the
-      // previous bucket's start window up to its own.
-      constexpr int PER = kBins / kTailThreads;
-      uint32_t* lb = sm.u.st.hist;  // the local histogram is flushed: reuse for offsets
-      const int t0 = threadIdx.x * PER;
-      uint32_t cnt[PER], sum = 0, big = 0;
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        cnt[j] = ld_coh(&ctl->bcount[t0 + j]);
-        sum += cnt[j];
-        big = cnt[j] > big ? cnt[j] : big;
-      }
-      sm.scan[threadIdx.x] = sum;
+    for (int o = 1; o < kTailThreads; o <<= 1) {
+      const uint32_t x = threadIdx.x >= (unsigned)o ? sm.scan[threadIdx.x - o] : 0u;
       __syncthreads();
-      for (int o = 1; o < kTailThreads; o <<= 1) {
-        const uint32_t x = threadIdx.x >= (unsigned)o ? sm.scan[threadIdx.x - o] : 0u;
-        __syncthreads();
-        sm.scan[threadIdx.x] += x;
-        __syncthreads();
-      }
-      uint32_t off = sm.scan[threadIdx.x] - sum;
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        lb[t0 + j] = off;
-        st_coh(&ctl->boff[t0 + j], off);
-        off += cnt[j];
-      }
-      if (threadIdx.x == kTailThreads - 1) st_coh(&ctl->boff[kBins], off);
+      sm.scan[threadIdx.x] += x;
       __syncthreads();
-      const uint32_t nwin = (nc + kGroup - 1) / kGroup;
-      if (big > kGroup || nwin > (uint32_t)kBins) atomicOr(&ctl->bigbucket, 1u);
-      if (nwin <= (uint32_t)kBins) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const uint32_t b = t0 + j;
-          const int64_t wb = lb[b] / kGroup;
-          const int64_t wp = b == 0 ? -1 : (int64_t)(lb[b - 1] / kGroup);
-          for (int64_t w = wp + 1; w <= wb && w <= (int64_t)nwin; ++w) st_coh(&ctl->gfirst[w], b);
-        }
-        if (threadIdx.x == kTailThreads - 1)
-          for (uint32_t w = lb[kBins - 1] / kGroup + 1; w <= nwin; ++w) st_coh(&ctl->gfirst[w], (uint32_t)kBins);
-        if (threadIdx.x == 0) st_coh(&ctl->ngroups, nwin);
-      }
-      stamp(ctl, PH_B1);
-      raise_ready(&ph[PH_B1]);
     }
-    wait_ready(&ph[PH_B1], ctl);
+    uint32_t off = sm.scan[threadIdx.x] - sum;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      lb[t0 + j] = off;
+      st_coh(&ctl->boff[t0 + j], off);
+      if (off < a.k && a.k <= off + cnt[j]) {  // exactly one bucket holds slot k-1
+        sm.out[0] = t0 + j;
+        sm.out[1] = off + cnt[j];
+      }
+      off += cnt[j];
+    }
+    if (threadIdx.x == kTailThreads - 1) st_coh(&ctl->boff[kBins], off);
+    __syncthreads();
+    const uint32_t bstar = sm.out[0], lim = sm.out[1], total = sm.scan[kTailThreads - 1];
+    uint32_t big = 0;  // fullest bucket up to b*
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if ((uint32_t)(t0 + j) <= bstar) big = cnt[j] > big ? cnt[j] : big;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint32_t y = (uint32_t)__shfl_xor((int)big, o);
+      big = y > big ? y : big;
+    }
+    if (lane_id() == 0) sm.rwave[threadIdx.x >> 6] = big;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTailThreads / 64; ++i) big = sm.rwave[i] > big ? sm.rwave[i] : big;
+    // every survivor was counted once: a mismatch is an internal error
+    const bool bad = bstar >= (uint32_t)kBins || total != ld_coh(&ctl->nc);
+    const uint32_t nwin = (lim + kGroup - 1) / kGroup;
+    if (bad || big > kGroup || nwin > (uint32_t)kBins) {
+      if (threadIdx.x == 0) {
+        atomicOr(&ctl->bigbucket, 1u);
+        if (bad) flag_err(ctl, ERR_SELECT);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t b = t0 + j;
+        if (b > bstar) break;
+        const int64_t wb = lb[b] / kGroup;
+        const int64_t wp = b == 0 ? -1 : (int64_t)(lb[b - 1] / kGroup);
+        for (int64_t w = wp + 1; w <= wb; ++w) st_coh(&ctl->gfirst[w], b);
+        if (b == bstar)
+          for (uint32_t w = (uint32_t)wb + 1; w <= nwin; ++w) st_coh(&ctl->gfirst[w], bstar + 1);
+      }
+      if (threadIdx.x == 0) {
+        st_coh(&ctl->ngroups, nwin);
+        st_coh(&ctl->bstar, bstar);
+      }
+    }
+    stamp(ctl, PH_B1);
+    raise_ready(&ph[PH_B1]);
   }
+  wait_ready(&ph[PH_B1], ctl);
   if (ld_coh(&ctl->bigbucket) == 0u) {
-    // B2: scatter into bucket order
+    // B2: scatter the buckets up to b* into bucket order
     {
+      const uint32_t bstar = ld_coh(&ctl->bstar);
       const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
       uint32_t mine = 0;
       // per claim: every load first; bucket counts and each element's rank in
@@ -1001,8 +1011,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
           const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
-          bb[j] = 2047u - (uint32_t)((comp(kk[j], ii[j]) - cmin) >> bsh);
-          rk[j] = i < nc ? atomicAdd(&lh[bb[j]], 1u) : 0u;
+          bb[j] = i < nc ? bm(comp(kk[j], ii[j])) : (uint32_t)kBins;
+          rk[j] = bb[j] <= bstar ? atomicAdd(&lh[bb[j]], 1u) : 0u;
         }
         __syncthreads();
         uint32_t base[PER];
@@ -1018,8 +1028,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
-          if (i < nc) {
+          if (bb[j] <= bstar) {
             const uint32_t slot = lh[bb[j]] + rk[j];
             if (slot < a.cap_s) {
               st_coh(&a.skey[slot], kk[j]);

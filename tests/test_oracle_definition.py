@@ -7,7 +7,14 @@ import oracle
 from oracle import stages
 import oracle_pins as pins
 
-ROUTES = [oracle.topk_sort, oracle.topk_select, oracle.topk_heap]
+
+
+def topk_threaded3(values, k, dtype, largest=True):
+    """The threaded route with three parts, so tiny inputs still exercise the merge."""
+    return oracle.topk_threaded(values, k, dtype, largest, threads=3)
+
+
+ROUTES = [oracle.topk_sort, oracle.topk_select, oracle.topk_heap, topk_threaded3]
 
 
 @pytest.mark.parametrize("fn", ROUTES + [oracle.topk_bruteforce], ids=lambda f: f.__name__)
@@ -59,6 +66,8 @@ def test_routes_agree_random(dtype, largest):
             if n <= 1000:
                 c = oracle.topk_heap(v, k, dtype, largest)[1]
                 assert (a == c).all()
+            for threads in (2, 5, 16):
+                assert (a == oracle.topk_threaded(v, k, dtype, largest, threads=threads)[1]).all()
 
 
 def test_argument_errors():
@@ -76,3 +85,24 @@ def test_delegates_bruteforce():
 
 def test_paper_worked_example():
     pins.pin_paper_example(stages)
+
+
+@pytest.mark.parametrize("kind", ["heavydup", "allequal", "ascending", "descending"])
+def test_threaded_route_ties_across_parts(kind):
+    """Ties and runs that straddle part boundaries: the merged answer is the
+    definition's (positions of tied keys in ascending order across parts)."""
+    n = 10007
+    if kind == "heavydup":
+        v = np.random.default_rng(3).integers(0, 5, size=n, dtype=np.uint32)
+    elif kind == "allequal":
+        v = np.full(n, 7, dtype=np.uint32)
+    elif kind == "ascending":
+        v = np.arange(n, dtype=np.uint32) // 3
+    else:
+        v = (n - np.arange(n, dtype=np.uint32)) // 3
+    for k in (1, 3, 100, 4000, n):
+        for threads in (1, 2, 7, 64):
+            for largest in (True, False):
+                want = oracle.topk_sort(v, k, "u32", largest)[1]
+                got = oracle.topk_threaded(v, k, "u32", largest, threads=threads)[1]
+                assert (got == want).all(), (kind, k, threads, largest)

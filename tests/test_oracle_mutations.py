@@ -79,6 +79,23 @@ def _i32_unsigned(values, k, dtype, largest=True):
     return v[o], o
 
 
+def _threaded_part_share(values, k, dtype):
+    # mistake: each of three parts contributes only its share ceil(k / 3) of
+    # candidates instead of its own top k
+    v = np.asarray(values)
+    n = v.shape[0]
+    bounds = [n * i // 3 for i in range(4)]
+    parts = []
+    for i in range(3):
+        lo, hi = bounds[i], bounds[i + 1]
+        if hi > lo:
+            parts.append(T.topk_select(v[lo:hi], min(-(-k // 3), hi - lo), dtype)[1] + lo)
+    cand = np.concatenate(parts)
+    key = order.rank_key(v[cand], dtype)
+    idx = cand[np.lexsort((cand, -key))[:k]]
+    return v[idx], idx
+
+
 def _with_key(fn_key):
     def f(values, k, dtype):
         n = values.shape[0]
@@ -96,6 +113,7 @@ MUTANTS = {
     "heap_tiebreak": (_heap_wrong_tiebreak, pins.pin_exhaustive_u32),
     "smallest_ties_descending": (_smallest_ties_desc, pins.pin_smallest_and_i32),
     "i32_unsigned_order": (_i32_unsigned, pins.pin_smallest_and_i32),
+    "threaded_part_share": (_threaded_part_share, pins.pin_exhaustive_u32),
 }
 
 

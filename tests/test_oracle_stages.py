@@ -73,3 +73,39 @@ def test_alpha_rule_monotone():
     assert stages.alpha_rule(2 ** 30, 2 ** 17) == 8
     assert stages.alpha_rule(2 ** 20, 2 ** 20) == 1
     assert stages.alpha_rule(16, 2 ** 20) == 0
+
+
+def test_workload_statistic_paper_point():
+    """The paper's workload statistic (Section 6, workload against |V|): with
+    beta = 1 on the uniform dataset at |V| = 2^30 and k = 2^19, the delegate
+    vector plus the filtered concatenated vector hold 0.83% of |V|.  The stage
+    model reproduces it at Rule 4's alpha (7): |D| / |V| = 2^-7 = 0.78%, and
+    the concatenation holds the elements ranked at or above t (about
+    k (1 + k / 2S), 0.05% of |V|).  The concatenation's size is a random
+    quantity; its spread here (a few hundred elements, under 0.0001% of |V|)
+    is far inside the tolerance of the printed two decimals, [0.825%, 0.835%).
+    The model runs in chunks of whole subranges so it fits in memory."""
+    n, k, beta = 1 << 30, 1 << 19, 1
+    alpha = stages.alpha_rule(n, k)
+    assert alpha == 7
+    L = 1 << alpha
+    x = synth.uniform_u32(n, synth.DEFAULT_SEED)
+    chunk = 1 << 24
+    dks, dis = [], []
+    for lo in range(0, n, chunk):
+        dk, di = stages.delegates(x[lo:lo + chunk], "u32", alpha, beta)
+        dks.append(dk)
+        dis.append(di + lo)
+    dkey, didx = np.concatenate(dks), np.concatenate(dis)
+    del dks, dis
+    taken, t = stages.first_topk(dkey, didx, k)
+    qual = stages.qualifying(taken, t)
+    concat = int(np.count_nonzero(taken & ~qual[:, None]))  # delegates taken without their subrange
+    for lo in range(0, n, chunk):
+        key = oracle.rank_key(x[lo:lo + chunk], "u32")
+        pos = np.arange(lo, lo + chunk, dtype=np.int64)
+        inq = np.repeat(qual[lo // L:(lo + chunk) // L], L)
+        concat += int(np.count_nonzero(inq & stages.at_or_above(key, pos, t)))
+    ratio = (dkey.size + concat) / n
+    assert 0.00825 <= ratio < 0.00835, ratio
+    assert k <= concat <= 1.1 * k
