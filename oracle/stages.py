@@ -24,6 +24,9 @@ Readings where the paper is silent or loose (each listed in the design notes):
 * a last subrange shorter than 2^alpha is allowed; a subrange with fewer than
   beta elements pads its delegate list with (lowest key, INVALID_INDEX);
 * fewer than k real delegates: no threshold, every subrange qualifies.
+
+The padding key below is below every rank key of the 32-bit key types; the
+stage model serves those (64-bit keys are checked on final results).
 """
 from __future__ import annotations
 

@@ -3,7 +3,8 @@
 Problem statement (Section 1): top-k returns the k largest elements of V,
 k-selection the k-th largest.  This project fixes what the paper leaves open:
 
-* order: ``rank_key`` (uint32 and int32 as is; float32 by IEEE totalOrder);
+* order: ``rank_key`` (unsigned and signed integers in their own order; floats
+  by IEEE totalOrder; 32- and 64-bit keys);
 * ties: among equal keys the lower position ranks first, so position i
   precedes j iff key[i] > key[j] or (key[i] == key[j] and i < j);
 * output: the k first positions in that order, i.e. values sorted by key
@@ -31,9 +32,10 @@ from .order import rank_key
 
 def _key(values: np.ndarray, dtype: str, largest: bool) -> np.ndarray:
     """Ranking key: a larger number ranks first (for the k smallest, the
-    negated order key)."""
+    complemented order key: ~x = -1 - x reverses the order like a negation
+    but cannot overflow at the int64 minimum)."""
     key = rank_key(values, dtype)
-    return key if largest else -key
+    return key if largest else ~key
 
 
 def _check(values: np.ndarray, k: int) -> int:
@@ -66,7 +68,7 @@ def topk_sort(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     """Sort-and-choose (Section 2.2): sort every position by (key desc, index asc), keep k."""
     n = _check(values, k)
     key = _key(values, dtype, largest)
-    order = np.lexsort((np.arange(n, dtype=np.int64), -key))
+    order = np.lexsort((np.arange(n, dtype=np.int64), ~key))
     idx = order[:k].astype(np.int64)
     return np.asarray(values)[idx], idx
 
@@ -88,7 +90,7 @@ def topk_select(values: np.ndarray, k: int, dtype: str, largest: bool = True):
     g = above.shape[0]
     ties = np.flatnonzero(key == T)[: k - g]
     idx = np.concatenate([above, ties]).astype(np.int64)
-    order = np.lexsort((idx, -key[idx]))
+    order = np.lexsort((idx, ~key[idx]))
     idx = idx[order]
     return np.asarray(values)[idx], idx
 
@@ -151,7 +153,7 @@ def topk_threaded(values: np.ndarray, k: int, dtype: str, largest: bool = True, 
         raise errors[0]
     cand = np.concatenate(parts)
     key = _key(values[cand], dtype, largest)
-    idx = cand[np.lexsort((cand, -key))[:k]].astype(np.int64)
+    idx = cand[np.lexsort((cand, ~key))[:k]].astype(np.int64)
     return values[idx], idx
 
 

@@ -69,7 +69,10 @@ def _lib():
         lib.synth_uniform_u32.argtypes = [u64, u64, p]
         lib.synth_mod_u32.argtypes = [u64, u64, ctypes.c_uint32, p]
         lib.synth_normal_f32.argtypes = [u64, u64, p]
-        for f in (lib.synth_u64, lib.synth_uniform_u32, lib.synth_mod_u32, lib.synth_normal_f32):
+        lib.synth_normal_f64.argtypes = [u64, u64, p]
+        lib.synth_mod_u64.argtypes = [u64, u64, u64, p]
+        for f in (lib.synth_u64, lib.synth_uniform_u32, lib.synth_mod_u32, lib.synth_normal_f32,
+                  lib.synth_normal_f64, lib.synth_mod_u64):
             f.restype = None
         _LIB = lib
     return _LIB
@@ -121,7 +124,42 @@ def heavy_dup_u32(n: int, seed: int = DEFAULT_SEED, distinct: int = 16) -> np.nd
     return out
 
 
+def uniform_u64(n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """n i.i.d. uint64 uniform over [0, 2^64): the stream itself."""
+    out = np.empty(n, dtype=np.uint64)
+    _lib().synth_u64(_seed64(seed), 0, n, out.ctypes.data)
+    return out
+
+
+def normal_f64(n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """n float64 draws of N(0, 1): normal_f32's Box-Muller draw, not rounded."""
+    out = np.empty(n, dtype=np.float64)
+    _lib().synth_normal_f64(_seed64(seed), n, out.ctypes.data)
+    return out
+
+
+def heavy_dup_u64(n: int, seed: int = DEFAULT_SEED, distinct: int = 16) -> np.ndarray:
+    """uint64 values uniform over [0, distinct)."""
+    out = np.empty(n, dtype=np.uint64)
+    _lib().synth_mod_u64(_seed64(seed), n, distinct, out.ctypes.data)
+    return out
+
+
 # numpy restatements of the same streams, used to check the C library.
+def ref_uniform_u64(n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    return u64_stream(seed, 0, n)
+
+
+def ref_normal_f64(n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    x = u64_stream(seed, 0, 2 * n)
+    a = (x[0::2] >> np.uint64(11)).astype(np.float64)
+    b = (x[1::2] >> np.uint64(11)).astype(np.float64)
+    u1 = (a + 1.0) * (1.0 / 9007199254740992.0)
+    u2 = b * (1.0 / 9007199254740992.0)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+
 def ref_uniform_u32(n: int, seed: int = DEFAULT_SEED) -> np.ndarray:
     return (u64_stream(seed, 0, n) >> np.uint64(32)).astype(np.uint32)
 
@@ -157,7 +195,7 @@ def derive_seed(base: int, i: int) -> int:
 
 
 def keys(kind: str, n: int, seed: int = DEFAULT_SEED) -> tuple[np.ndarray, str]:
-    """Named workloads -> (array, dtype tag 'u32', 'f32' or 'i32').
+    """Named workloads -> (array, dtype tag 'u32', 'f32', 'i32', 'u64', 'i64' or 'f64').
 
     uniform_i32 is the uniform uint32 stream read as int32 (uniform over the
     whole signed range); smallrange_i32 maps it onto [-1000, 1000] (ties and
@@ -177,6 +215,23 @@ def keys(kind: str, n: int, seed: int = DEFAULT_SEED) -> tuple[np.ndarray, str]:
         return uniform_u32(n, seed).view(np.int32), "i32"
     if kind == "smallrange_i32":
         return (heavy_dup_u32(n, seed, 2001).astype(np.int64) - 1000).astype(np.int32), "i32"
+    if kind == "uniform_u64":
+        return uniform_u64(n, seed), "u64"
+    if kind == "uniform_i64":
+        return uniform_u64(n, seed).view(np.int64), "i64"
+    if kind == "normal_f64":
+        return normal_f64(n, seed), "f64"
+    if kind == "sorted_f64":
+        x = normal_f64(n, seed)
+        x.sort()
+        return x, "f64"
+    if kind == "heavydup_u64":
+        return heavy_dup_u64(n, seed), "u64"
+    if kind == "smallrange_i64":
+        return heavy_dup_u64(n, seed, 2001).astype(np.int64) - 1000, "i64"
+    if kind == "highword_u64":
+        # keys whose high 32 bits take only 16 values: order is decided by the low word
+        return (heavy_dup_u64(n, seed, 16) << np.uint64(32)) | (uniform_u64(n, seed + 1) >> np.uint64(32)), "u64"
     raise ValueError(f"unknown workload kind {kind!r}")
 
 

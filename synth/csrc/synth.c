@@ -50,3 +50,23 @@ void synth_normal_f32(uint64_t seed, uint64_t n, float* out) {
     out[j] = (float)(sqrt(-2.0 * log(u1)) * cos(two_pi * u2));
   }
 }
+
+/* The same Box-Muller draw kept in double (64-bit keys). */
+void synth_normal_f64(uint64_t seed, uint64_t n, double* out) {
+  const uint64_t b = mix64(seed);
+  const double inv53 = 1.0 / 9007199254740992.0;
+  const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < (int64_t)n; ++j) {
+    uint64_t x1 = elem(b, 2 * (uint64_t)j), x2 = elem(b, 2 * (uint64_t)j + 1);
+    double u1 = ((double)(x1 >> 11) + 1.0) * inv53;
+    double u2 = (double)(x2 >> 11) * inv53;
+    out[j] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+  }
+}
+
+void synth_mod_u64(uint64_t seed, uint64_t n, uint64_t modulus, uint64_t* out) {
+  const uint64_t b = mix64(seed);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < (int64_t)n; ++j) out[j] = elem(b, (uint64_t)j) % modulus;
+}

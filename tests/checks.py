@@ -29,27 +29,30 @@ def check_exact(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_
     assert gi.shape == (k,), (tag, gi.shape)
     bad = np.flatnonzero(gi != want_idx)
     assert bad.size == 0, f"{tag}: {bad.size} index mismatches, first at slot {bad[0]}: got {gi[bad[0]]} want {want_idx[bad[0]]}"
-    gv = np.asarray(got_vals).view(np.uint32)
-    wv = np.asarray(want_vals).view(np.uint32)
+    gv = oracle.order.bits(got_vals)
+    wv = oracle.order.bits(want_vals)
     assert (gv == wv).all(), f"{tag}: values differ"
 
 
 def check_invariants(keys: np.ndarray, k: int, dtype: str, got_vals: np.ndarray, got_idx: np.ndarray, tag="",
                      largest: bool = True):
-    sign = 1 if largest else -1
+    def order_key(v):  # larger ranks first; ~ reverses the order without overflow
+        rk = oracle.rank_key(v, dtype)
+        return rk if largest else ~rk
+
     n = keys.shape[0]
     gi = np.asarray(got_idx).view(np.uint32).astype(np.int64)
-    gv = np.asarray(got_vals).view(np.uint32)
+    gv = oracle.order.bits(got_vals)
     assert gi.shape == (k,), tag
     assert (gi >= 0).all() and (gi < n).all(), f"{tag}: position out of range"
     assert np.unique(gi).shape[0] == k, f"{tag}: repeated positions"  # I1
-    kb = keys.view(np.uint32)
+    kb = oracle.order.bits(keys)
     assert (kb[gi] == gv).all(), f"{tag}: values are not the keys at the positions"  # I2
-    rk = sign * oracle.rank_key(keys[gi], dtype)
+    rk = order_key(keys[gi])
     ok = (rk[:-1] > rk[1:]) | ((rk[:-1] == rk[1:]) & (gi[:-1] < gi[1:]))
     assert ok.all(), f"{tag}: outputs not in (key desc, position asc) order"  # I3
     kth = rk[-1]
-    full = sign * oracle.rank_key(keys, dtype)
+    full = order_key(keys)
     greater = int(np.count_nonzero(full > kth))
     at_least = greater + int(np.count_nonzero(full == kth))
     assert greater < k <= at_least, f"{tag}: k-th value wrong ({greater}, {k}, {at_least})"  # I4

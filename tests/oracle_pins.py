@@ -260,3 +260,114 @@ def pin_kth_smallest(kth_fn, seed: int = 17) -> None:
             assert int(kth_fn(v, k, "u32", largest=False)) == int(np.sort(v)[k - 1])
             assert int(kth_fn(w, k, "i32", largest=False)) == int(np.sort(w)[k - 1])
             assert int(kth_fn(w, k, "i32")) == int(np.sort(w)[::-1][k - 1])
+
+
+U64_ALPHABET = np.array([0, 1, 1 << 63, (1 << 64) - 1], dtype=np.uint64)
+I64_ALPHABET = np.array([-(1 << 63), -1, 0, 1, (1 << 63) - 1], dtype=np.int64)
+
+
+def f64_chain() -> np.ndarray:
+    """float64 bit patterns in ascending IEEE 754 totalOrder."""
+    pats = [
+        0xFFFFFFFFFFFFFFFF,  # -NaN, largest payload
+        0xFFF8000000000001,  # -NaN, quiet, small payload
+        0xFFF0000000000001,  # -NaN, signalling, smallest payload
+        0xFFF0000000000000,  # -inf
+        0xFFEFFFFFFFFFFFFF,  # -max finite
+        0xBFF0000000000001,  # -(1 + 2^-52)
+        0xBFF0000000000000,  # -1
+        0x8010000000000000,  # -min normal
+        0x800FFFFFFFFFFFFF,  # -max subnormal
+        0x8000000000000001,  # -min subnormal
+        0x8000000000000000,  # -0
+        0x0000000000000000,  # +0
+        0x0000000000000001,  # +min subnormal
+        0x000FFFFFFFFFFFFF,  # +max subnormal
+        0x0010000000000000,  # +min normal
+        0x3FF0000000000000,  # +1
+        0x3FF0000000000001,  # +(1 + 2^-52): differs from +1 in the lowest bit only
+        0x7FEFFFFFFFFFFFFF,  # +max finite
+        0x7FF0000000000000,  # +inf
+        0x7FF0000000000001,  # +NaN, signalling, smallest payload
+        0x7FF8000000000000,  # +NaN, quiet
+        0x7FFFFFFFFFFFFFFF,  # +NaN, largest payload
+    ]
+    return np.array(pats, dtype=np.uint64)
+
+
+def pin_wide(topk_fn, seed: int = 19) -> None:
+    """64-bit keys (uint64, int64, float64), both orders, against Python's own
+    sort of Python integers, numpy's argmax / argmin / stable argsort / sort,
+    and the hand-ordered float64 totalOrder chain."""
+    rng = np.random.default_rng(seed)
+    for dt, alphabet, max_len in (("u64", U64_ALPHABET, 4), ("i64", I64_ALPHABET, 3)):
+        for n in range(1, max_len + 1):
+            for combo in itertools.product(range(len(alphabet)), repeat=n):
+                v = alphabet[list(combo)]
+                py = [int(x) for x in v]
+                up = sorted(range(n), key=lambda i: (py[i], i))
+                down = sorted(range(n), key=lambda i: (-py[i], i))
+                for k in range(1, n + 1):
+                    vals, idx = topk_fn(v, k, dt)
+                    assert list(map(int, idx)) == down[:k], (dt, py, k, list(idx))
+                    assert (np.asarray(vals).view(np.uint64) == v[down[:k]].view(np.uint64)).all()
+                    assert list(map(int, topk_fn(v, k, dt, largest=False)[1])) == up[:k], (dt, py, k)
+    # values above 2^53 that differ in their lowest bits (a float64 detour, or
+    # the high 32 bits alone, would tie them)
+    base = (1 << 60) + (7 << 32)
+    v = np.array([base + 1, base, base + 2, base + (1 << 32), base - 1], dtype=np.uint64)
+    assert list(map(int, topk_fn(v, 5, "u64")[1])) == [3, 2, 0, 1, 4]
+    w = v.astype(np.int64) * -1
+    assert list(map(int, topk_fn(w, 5, "i64")[1])) == [4, 1, 0, 2, 3]
+    # k = 1: numpy's first argmax / argmin
+    for n in (1, 2, 17, 1000):
+        u = rng.integers(0, 50, size=n).astype(np.uint64) << np.uint64(58)
+        assert int(topk_fn(u, 1, "u64")[1][0]) == int(np.argmax(u))
+        assert int(topk_fn(u, 1, "u64", largest=False)[1][0]) == int(np.argmin(u))
+        s = rng.integers(-25, 25, size=n).astype(np.int64) << np.int64(50)
+        assert int(topk_fn(s, 1, "i64")[1][0]) == int(np.argmax(s))
+        assert int(topk_fn(s, 1, "i64", largest=False)[1][0]) == int(np.argmin(s))
+        f = rng.integers(-8, 8, size=n) * 0.5 + 0.25
+        assert int(topk_fn(f, 1, "f64")[1][0]) == int(np.argmax(f))
+        assert int(topk_fn(f, 1, "f64", largest=False)[1][0]) == int(np.argmin(f))
+    # k = n, the k smallest: numpy's stable ascending argsort (ties in position order)
+    for n in (1, 5, 300):
+        u = rng.integers(0, 20, size=n).astype(np.uint64) * np.uint64(0x0F00000000000001)
+        assert (np.asarray(topk_fn(u, n, "u64", largest=False)[1]) == np.argsort(u, kind="stable")).all()
+        s = rng.integers(-10, 10, size=n).astype(np.int64) * np.int64(0x0300000000000001)
+        assert (np.asarray(topk_fn(s, n, "i64", largest=False)[1]) == np.argsort(s, kind="stable")).all()
+        f = rng.integers(-8, 8, size=n) * 0.5 + 0.25  # no NaN, no -0: value order is totalOrder
+        assert (np.asarray(topk_fn(f, n, "f64", largest=False)[1]) == np.argsort(f, kind="stable")).all()
+    # distinct values, largest first: numpy's ascending argsort reversed
+    u = rng.permutation(np.arange(1000, dtype=np.uint64) * np.uint64(0x00FF00FF00FF00FF))
+    assert (np.asarray(topk_fn(u, 1000, "u64")[1]) == np.argsort(u)[::-1]).all()
+    # float64 totalOrder both ways: the hand-ordered chain, shuffled
+    chain = f64_chain()
+    perm = rng.permutation(chain.shape[0])
+    vals, _ = topk_fn(chain[perm].view(np.float64), chain.shape[0], "f64")
+    assert (np.asarray(vals).view(np.uint64) == chain[::-1]).all(), [hex(x) for x in np.asarray(vals).view(np.uint64)]
+    vals, _ = topk_fn(chain[perm].view(np.float64), chain.shape[0], "f64", largest=False)
+    assert (np.asarray(vals).view(np.uint64) == chain).all()
+    # value multisets against numpy's sort
+    u = rng.integers(0, 2 ** 63, size=5000, dtype=np.int64).view(np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=5000).astype(np.uint64)
+    assert (np.asarray(topk_fn(u, 777, "u64")[0]) == np.sort(u)[::-1][:777]).all()
+    s = rng.integers(-2 ** 63, 2 ** 63 - 1, size=5000, dtype=np.int64)
+    assert (np.asarray(topk_fn(s, 777, "i64", largest=False)[0]) == np.sort(s)[:777]).all()
+    f = rng.standard_normal(5000) * 1e300
+    assert (np.asarray(topk_fn(f, 777, "f64")[0]) == np.sort(f)[::-1][:777]).all()
+
+
+def pin_kth_wide(kth_fn, seed: int = 23) -> None:
+    """k-th largest / smallest of 64-bit keys = numpy's sort at k-1."""
+    rng = np.random.default_rng(seed)
+    for n in (1, 9, 1000):
+        u = rng.integers(0, 30, size=n).astype(np.uint64) << np.uint64(59)
+        s = rng.integers(-15, 15, size=n).astype(np.int64) << np.int64(58)
+        f = rng.integers(-15, 15, size=n) * 0.125
+        for k in sorted({1, n, max(1, n // 3)}):
+            assert int(kth_fn(u, k, "u64")) == int(np.sort(u)[::-1][k - 1])
+            assert int(kth_fn(u, k, "u64", largest=False)) == int(np.sort(u)[k - 1])
+            assert int(kth_fn(s, k, "i64")) == int(np.sort(s)[::-1][k - 1])
+            assert int(kth_fn(s, k, "i64", largest=False)) == int(np.sort(s)[k - 1])
+            assert float(kth_fn(f, k, "f64")) == float(np.sort(f)[::-1][k - 1])

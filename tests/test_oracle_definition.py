@@ -45,8 +45,17 @@ def test_kth_smallest():
     pins.pin_kth_smallest(oracle.kth_value)
 
 
+@pytest.mark.parametrize("fn", ROUTES + [oracle.topk_bruteforce], ids=lambda f: f.__name__)
+def test_wide_keys(fn):
+    pins.pin_wide(fn)
+
+
+def test_kth_wide():
+    pins.pin_kth_wide(oracle.kth_value)
+
+
 @pytest.mark.parametrize("largest", [True, False])
-@pytest.mark.parametrize("dtype", ["u32", "f32", "i32"])
+@pytest.mark.parametrize("dtype", ["u32", "f32", "i32", "u64", "i64", "f64"])
 def test_routes_agree_random(dtype, largest):
     rng = np.random.default_rng(1)
     for n in (1, 2, 63, 64, 65, 1000, 4097):
@@ -55,6 +64,15 @@ def test_routes_agree_random(dtype, largest):
             v[rng.integers(0, n, size=n // 4)] = v[0]  # plant ties
         elif dtype == "i32":
             v = rng.integers(-2 ** 31, 2 ** 31, size=n).astype(np.int32)
+            v[rng.integers(0, n, size=n // 4)] = v[0]
+        elif dtype == "u64":
+            v = rng.integers(0, 2 ** 63, size=n, dtype=np.int64).view(np.uint64) * np.uint64(2)
+            v[rng.integers(0, n, size=n // 4)] = v[0]
+        elif dtype == "i64":
+            v = rng.integers(-2 ** 63, 2 ** 63 - 1, size=n, dtype=np.int64)
+            v[rng.integers(0, n, size=n // 4)] = v[0]
+        elif dtype == "f64":
+            v = rng.standard_normal(n)
             v[rng.integers(0, n, size=n // 4)] = v[0]
         else:
             v = rng.standard_normal(n).astype(np.float32)

@@ -105,6 +105,37 @@ def _with_key(fn_key):
     return f
 
 
+def _with_key_both(fn_key, flip=lambda k: ~k):
+    """A sort-and-choose route on a (possibly broken) rank key, both orders."""
+    def f(values, k, dtype, largest=True):
+        n = values.shape[0]
+        key = fn_key(values, dtype)
+        key = key if largest else flip(key)
+        o = np.lexsort((np.arange(n), ~key))[:k]
+        return values[o], o
+    return f
+
+
+def _key_u64_signed(values, dtype):
+    # mistake: uint64 ranked by its signed view (2^63 and above rank below 0)
+    if dtype == "u64":
+        return np.asarray(values).view(np.int64)
+    return order.rank_key(values, dtype)
+
+
+def _key_f64_value(values, dtype):
+    # mistake: float64 compared by value (loses -0 < +0 and the NaN places)
+    if dtype == "f64":
+        return np.asarray(values).astype(np.float64)
+    return order.rank_key(values, dtype)
+
+
+def _key_high_word(values, dtype):
+    # mistake: 64-bit keys ranked by their high 32 bits only
+    key = order.rank_key(values, dtype)
+    return key >> 32 if dtype in ("u64", "i64", "f64") else key
+
+
 MUTANTS = {
     "float_by_value": (_with_key(_key_float_value), pins.pin_float_order),
     "no_negative_flip": (_with_key(_key_no_flip), pins.pin_float_order),
@@ -114,6 +145,11 @@ MUTANTS = {
     "smallest_ties_descending": (_smallest_ties_desc, pins.pin_smallest_and_i32),
     "i32_unsigned_order": (_i32_unsigned, pins.pin_smallest_and_i32),
     "threaded_part_share": (_threaded_part_share, pins.pin_exhaustive_u32),
+    "u64_signed_view": (_with_key_both(_key_u64_signed), pins.pin_wide),
+    "f64_by_value": (_with_key_both(_key_f64_value, flip=lambda k: -k), pins.pin_wide),
+    "wide_high_word_only": (_with_key_both(_key_high_word), pins.pin_wide),
+    # mistake: the k smallest by negating the key (-(-2^63) wraps to -2^63)
+    "i64_negated_smallest": (_with_key_both(order.rank_key, flip=lambda k: -k), pins.pin_wide),
 }
 
 

@@ -11,6 +11,11 @@ def test_c_matches_numpy():
             assert (synth.heavy_dup_u32(n, seed) == synth.ref_heavy_dup_u32(n, seed)).all()
             a, b = synth.normal_f32(n, seed), synth.ref_normal_f32(n, seed)
             assert np.abs(a - b).max() <= 1e-6  # libm vs numpy may differ in the last bit
+            assert (synth.uniform_u64(n, seed) == synth.ref_uniform_u64(n, seed)).all()
+            assert (synth.heavy_dup_u64(n, seed) == synth.u64_stream(seed, 0, n) % np.uint64(16)).all()
+            c, d = synth.normal_f64(n, seed), synth.ref_normal_f64(n, seed)
+            assert np.abs(c - d).max() <= 1e-12
+            assert (np.float32(c) == a).all() or np.abs(np.float32(c) - a).max() <= 1e-6
 
 
 def test_splitmix_reference_values():
@@ -31,5 +36,11 @@ def test_distributions():
     assert (np.diff(s) >= 0).all()
     h = synth.heavy_dup_u32(1 << 16, 5)
     assert set(np.unique(h).tolist()) == set(range(16))
+    z64 = synth.normal_f64(1 << 20, 5)
+    assert abs(z64.mean()) < 0.005 and abs(z64.std() - 1) < 0.005
+    u64 = synth.uniform_u64(1 << 20, 5)
+    assert abs((u64 >> np.uint64(11)).astype(np.float64).mean() / 2 ** 53 - 0.5) < 0.002
+    x, dt = synth.keys("highword_u64", 4096, 5)
+    assert dt == "u64" and np.unique(x >> np.uint64(32)).shape[0] == 16
     li = synth.log_uniform_int(10000, 10, 20, 5)
     assert li.min() >= 2 ** 10 and li.max() <= 2 ** 20
