@@ -54,7 +54,8 @@ typedef enum {
   DRTOPK_EINVAL = 1,
   DRTOPK_ENOMEM = 2,
   DRTOPK_EDEVICE = 3,
-  DRTOPK_EUNSUPPORTED = 4
+  DRTOPK_EUNSUPPORTED = 4,
+  DRTOPK_ESCRATCH = 5 /* topk_select_noalloc: the call needs more than its fixed workspace */
 } drtopk_status_t;
 
 /* Top-k (paper, Section 1).
@@ -68,6 +69,28 @@ typedef enum {
  *   stream   hipStream_t or NULL */
 int topk_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals,
                 uint32_t* out_idx, void* stream);
+
+/* topk_select for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, results (bit for bit) and kernels as topk_select, but the
+ * workspace is a fixed device array of 128 MiB built into the library, one
+ * copy per device, held until the process ends; the call allocates nothing.
+ * Its first call on a device (with that device current) looks the array up
+ * and synchronises the device once: make that call outside graph capture.
+ *   - DRTOPK_ESCRATCH, with nothing enqueued, if the call's workspace exceeds
+ *     the array (the workspace is drtopk_footprint(n, k, dtype) minus the
+ *     4n + 8k + 4 bytes of input and outputs): at n = 2^30 it fits up to
+ *     k = 1024, at n = 2^26 up to k = 16384, and for n <= 2^22 every k fits.
+ *   - Every call on a device shares that device's array, which keeps the last
+ *     call's contents; each call clears what it needs.  Calls whose work
+ *     overlaps on one device (other streams, other host threads) race and
+ *     give wrong results: order them on one stream or with events.
+ *   - Failed internal checks are recorded on the device and reported by the
+ *     next drtopk_check on the device (on any stream, once the calls
+ *     concerned have finished; calling it on the calls' stream ensures that).
+ * Other errors as topk_select. */
+int topk_select_noalloc(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
+                        void* stream);
 
 /* k-selection (paper, Section 1): writes the k-th largest value (1 element of
  * `dtype`, device memory) to out_kth.  Same argument rules as topk_select. */
@@ -334,7 +357,8 @@ enum {
 
 /* Synchronises `stream`, then reports and clears the check flags recorded by
  * the kernels of every call enqueued on it (on the current device) since the
- * previous drtopk_check of that stream: DRTOPK_OK and *flags = 0 if none,
+ * previous drtopk_check of that stream, together with those recorded by
+ * topk_select_noalloc calls on the device: DRTOPK_OK and *flags = 0 if none,
  * DRTOPK_EDEVICE with the OR of the flags otherwise (flags may be NULL).
  * DRTOPK_EDEVICE with *flags = 0 if the synchronisation itself fails. */
 int drtopk_check(void* stream, uint32_t* flags);

@@ -23,7 +23,8 @@ TUNING_PATH = os.path.join(HERE, "tuning.json")  # written by paper_2109_08219_a
 U32, F32, I32 = 0, 1, 2
 SMALLEST = 0x100  # OR-ed into a dtype code: the k smallest instead of the k largest
 _DTYPES = {"u32": U32, "f32": F32, "i32": I32}
-STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported"}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported",
+          5: "workspace exceeds the no-allocation scratch buffer"}
 
 
 CHECK_FLAGS = {1: "select", 2: "few survivors", 16: "capacity", 64: "wait timeout", 128: "sort group"}
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         sig = {
             "topk_select": [vp, u64, u32, i32, vp, vp, vp],
+            "topk_select_noalloc": [vp, u64, u32, i32, vp, vp, vp],
             "kth_select": [vp, u64, u32, i32, vp, vp],
             "topk_select_batched": [ctypes.POINTER(Problem), u32, vp],
             "topk_select_ex": [vp, u64, u32, i32, vp, vp, ctypes.POINTER(Options), ctypes.POINTER(Stats), vp],
@@ -227,6 +229,20 @@ def topk_select(keys, k: int, out_vals=None, out_idx=None, *, dtype=None, larges
     if check:
         check_stream(stream)
     return (out_vals, out_idx, st) if stats else (out_vals, out_idx)
+
+
+def topk_select_noalloc(keys, k: int, out_vals, out_idx=None, *, dtype=None, largest: bool = True,
+                        stream=None) -> None:
+    """topk_select into caller-provided outputs with the library's fixed device workspace: the
+    call allocates nothing (no torch or HIP allocation).  out_idx may be None (positions not
+    written).  Raises DrTopkError with status 5 if the problem needs more workspace than the
+    fixed buffer holds.  Calls on one device share that buffer: do not overlap them."""
+    code = _prep(keys, dtype, largest)
+    rc = lib().topk_select_noalloc(ctypes.c_void_p(keys.data_ptr()), keys.numel(), k, code,
+                                   ctypes.c_void_p(out_vals.data_ptr()),
+                                   ctypes.c_void_p(out_idx.data_ptr()) if out_idx is not None else None,
+                                   _stream(stream))
+    _check(rc, "topk_select_noalloc")
 
 
 def kth_select(keys, k: int, out=None, *, dtype=None, largest: bool = True, check: bool = False, stream=None):

@@ -355,6 +355,35 @@ uint32_t host_dec(int code, uint32_t u) {
   }
 }
 
+// Enqueues the kernels of plan p on stream s over the workspace `ws` (at
+// least p.total bytes; p.rec set).
+int enqueue_plan(const Plan& p, const void* keys, void* ws, void* out_vals, uint32_t* out_idx, void* out_kth,
+                 bool kth_only, bool filter_only, hipStream_t s) {
+  const uint32_t* kp = static_cast<const uint32_t*>(keys);
+  if (p.mode == 3) {
+    if (filter_only) return DRTOPK_EINVAL;
+    BatchDesc d{};
+    d.keys = kp;
+    d.n = p.n;
+    d.k = p.k;
+    d.dtype = (uint32_t)dt_code(p.dt);
+    d.alpha = (uint32_t)p.alpha;
+    d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
+    d.out_idx = kth_only ? nullptr : out_idx;
+    d.out_kth = static_cast<uint32_t*>(out_kth);
+    hipLaunchKernelGGL(k_one, dim3(1), dim3(kBT), 0, s, d, p.rec);
+    return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+  }
+  with_codec(dt_code(p.dt), [&](auto c) {
+    run_codec<decltype(c)::value>(p, kp, ws, static_cast<uint32_t*>(out_vals), out_idx,
+                                  static_cast<uint32_t*>(out_kth), kth_only, filter_only, s);
+  });
+  const hipError_t le = tl_launch_err;
+  tl_launch_err = hipSuccess;
+  if (hipGetLastError() != hipSuccess || le != hipSuccess) return DRTOPK_EDEVICE;
+  return DRTOPK_OK;
+}
+
 // Runs the whole path; `after` runs under the workspace lock after the
 // enqueue, with the plan, the workspace pointer and the stream.  pos_in_ws:
 // with out_idx NULL the output positions go to a workspace segment
@@ -381,29 +410,8 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
   p.rec = ws->rec;
   if (ws_pos) out_idx = at<uint32_t>(ws->ptr, p.off_pos);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const uint32_t* kp = static_cast<const uint32_t*>(keys);
-  if (p.mode == 3) {
-    if (filter_only) return DRTOPK_EINVAL;
-    BatchDesc d{};
-    d.keys = kp;
-    d.n = n;
-    d.k = k;
-    d.dtype = (uint32_t)dt_code(dtype);
-    d.alpha = (uint32_t)p.alpha;
-    d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
-    d.out_idx = kth_only ? nullptr : out_idx;
-    d.out_kth = static_cast<uint32_t*>(out_kth);
-    hipLaunchKernelGGL(k_one, dim3(1), dim3(kBT), 0, s, d, p.rec);
-    if (hipGetLastError() != hipSuccess) return DRTOPK_EDEVICE;
-    return after(p, ws->ptr, s);
-  }
-  with_codec(dt_code(dtype), [&](auto c) {
-    run_codec<decltype(c)::value>(p, kp, ws->ptr, static_cast<uint32_t*>(out_vals), out_idx,
-                                  static_cast<uint32_t*>(out_kth), kth_only, filter_only, s);
-  });
-  const hipError_t le = tl_launch_err;
-  tl_launch_err = hipSuccess;
-  if (hipGetLastError() != hipSuccess || le != hipSuccess) return DRTOPK_EDEVICE;
+  st = enqueue_plan(p, keys, ws->ptr, out_vals, out_idx, out_kth, kth_only, filter_only, s);
+  if (st) return st;
   return after(p, ws->ptr, s);
 }
 
@@ -568,6 +576,46 @@ __global__ void k_stream_gather(const uint32_t* sv, const uint32_t* si, uint32_t
 __global__ void k_zero_word(uint32_t* p) {
   if (threadIdx.x == 0) *p = 0;
 }
+__global__ void k_zero_words(uint32_t* p, uint32_t n) {
+  if (threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed workspace of topk_select_noalloc, for callers that cannot allocate
+// device memory: one copy of `scratch` per device, held until the process
+// ends.  Its first kScratchRec bytes are the check record of the no-alloc
+// calls (kErrWords words, set by failing kernel checks, cleared by
+// drtopk_check); the rest is the workspace of one call.  In host code the
+// array's name is not a device address: the address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr size_t kScratchRec = 256;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch (null on failure).
+void* scratch_base(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+  if (p) return p;
+  void* q = nullptr;
+  if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  // the record starts clear: the array is zero-initialised at load, and a
+  // kernel clears it once more so that nothing depends on that
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, nullptr, static_cast<uint32_t*>(q), (uint32_t)kErrWords);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return nullptr;
+  g_scratch_ptr[dev].store(q, std::memory_order_release);
+  return q;
+}
 
 int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
   if (!stats) return DRTOPK_OK;
@@ -622,6 +670,30 @@ int topk_select_ex(const void* keys, uint64_t n, uint32_t k, int dtype, void* ou
 int topk_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
                 void* stream) {
   return topk_select_ex(keys, n, k, dtype, out_vals, out_idx, nullptr, nullptr, stream);
+}
+
+int topk_select_noalloc(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx,
+                        void* stream) {
+  if (!out_vals) return DRTOPK_EINVAL;
+  int st = check_args(keys, n, k, dtype);
+  if (st) return st;
+  try {
+    Plan p;
+    st = make_plan(keys, n, k, dtype, nullptr, &p);
+    if (st) return st;
+    if (p.total > kScratchBytes - kScratchRec) return DRTOPK_ESCRATCH;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+    void* base = scratch_base(dev);
+    if (!base) return DRTOPK_EDEVICE;
+    void* ws = static_cast<char*>(base) + kScratchRec;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    p.rec = static_cast<uint32_t*>(base);
+    p.marks = false;  // no timing events
+    return enqueue_plan(p, keys, ws, out_vals, out_idx, nullptr, false, false, s);
+  } catch (...) {
+    return DRTOPK_EDEVICE;
+  }
 }
 
 int kth_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_kth, void* stream) {
@@ -1009,6 +1081,21 @@ int drtopk_check(void* stream, uint32_t* flags) {
     std::lock_guard<std::mutex> g(ws->mu);
     if (ws->rec) f |= read_record(ws->rec, true);
   }
+  // the no-alloc calls' record, in the device's scratch (if it was ever used)
+  void* sb = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev].load(std::memory_order_acquire) : nullptr;
+  if (sb) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t w[kErrWords] = {};
+    if (hipMemcpyAsync(w, sb, sizeof(w), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return DRTOPK_EDEVICE;
+    const uint32_t g = read_record(w, false);
+    if (g) {
+      hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, static_cast<uint32_t*>(sb), (uint32_t)kErrWords);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
+    }
+    f |= g;
+  }
   if (flags) *flags = f;
   return f ? DRTOPK_EDEVICE : DRTOPK_OK;
 }
@@ -1025,6 +1112,7 @@ const char* drtopk_status_string(int status) {
     case DRTOPK_ENOMEM: return "out of device memory";
     case DRTOPK_EDEVICE: return "device error";
     case DRTOPK_EUNSUPPORTED: return "unsupported";
+    case DRTOPK_ESCRATCH: return "workspace exceeds the no-allocation scratch buffer";
     default: return "unknown status";
   }
 }

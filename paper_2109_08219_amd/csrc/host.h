@@ -33,6 +33,7 @@ struct Plan {
   size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, off_skey = 0, off_sidx = 0, total = 0;
   size_t off_pos = 0;  // k output positions kept in the workspace (payload gathers without out_idx)
   uint32_t* rec = nullptr;  // the stream's check record (set by the caller before the enqueue)
+  bool marks = true;        // phase timing events may be recorded (drtopk_timing_enable)
 };
 
 extern thread_local hipError_t tl_launch_err;  // launches whose API reports errors directly

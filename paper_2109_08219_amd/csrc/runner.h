@@ -106,7 +106,7 @@ struct Runner {
   static void run(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
                   uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st) {
     PhaseMarks pm;
-    pm.begin(st);
+    if (p.marks) pm.begin(st);
     run_inner(p, keys, ws, out_vals, out_idx, out_kth, kth_only, filter_only, st, pm);
     pm.end(st);
   }

@@ -85,6 +85,20 @@ def test_payload_arguments_without_gpu():
     assert L.topk_select_payload(d, 100, 5, 0, d, 8, None, None, out, None) == 1  # no value output
 
 
+def test_noalloc_arguments_without_gpu():
+    L = drt.lib()
+    d = ctypes.c_void_p(16)
+    out = ctypes.c_void_p(32)
+    assert L.topk_select_noalloc(None, 100, 5, 0, out, None, None) == 1  # no input
+    assert L.topk_select_noalloc(d, 100, 5, 0, None, None, None) == 1  # no output
+    assert L.topk_select_noalloc(d, 100, 101, 0, out, None, None) == 1  # k > n
+    assert L.topk_select_noalloc(d, 100, 5, 3 | 0x200, out, None, None) == 1  # not a key type
+    # a workspace beyond the fixed 128 MiB is refused before any device work
+    assert L.topk_select_noalloc(d, 1 << 30, 131072, 0, out, None, None) == 5
+    assert L.topk_select_noalloc(d, 1 << 30, 2048, 1, out, None, None) == 5
+    assert drt.status_string(5).startswith("workspace exceeds")
+
+
 def test_host_stream_arguments_without_gpu():
     L = drt.lib()
     host = (ctypes.c_uint32 * 16)()
