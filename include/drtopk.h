@@ -46,8 +46,21 @@ extern "C" {
 /* Key types.  DRTOPK_SMALLEST may be OR-ed into any dtype argument or field:
  * the call then works on the k smallest keys (the paper's nearest-neighbour
  * and least-score uses, Section 6) -- out_vals ascending, ties by ascending
- * position, the k-th value the k-th smallest.  Everything else is the same. */
-typedef enum { DRTOPK_U32 = 0, DRTOPK_F32 = 1, DRTOPK_I32 = 2, DRTOPK_SMALLEST = 0x100 } drtopk_dtype_t;
+ * position, the k-th value the k-th smallest.  Everything else is the same.
+ * 64-bit keys (DRTOPK_U64, DRTOPK_I64, DRTOPK_F64; float64 by totalOrder) are
+ * 8 bytes each: keys and out_vals hold n and k 8-byte elements, out_kth one;
+ * key pointers must be 8-byte aligned.  They run one delegate per subrange
+ * (beta = 1) or the plain radix select; the per-call functions below take
+ * them unless their comment says otherwise. */
+typedef enum {
+  DRTOPK_U32 = 0,
+  DRTOPK_F32 = 1,
+  DRTOPK_I32 = 2,
+  DRTOPK_U64 = 3,
+  DRTOPK_I64 = 4,
+  DRTOPK_F64 = 5,
+  DRTOPK_SMALLEST = 0x100
+} drtopk_dtype_t;
 
 typedef enum {
   DRTOPK_OK = 0,

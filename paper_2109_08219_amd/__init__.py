@@ -20,9 +20,9 @@ LIB_PATH = os.path.join(HERE, "libdrtopk.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "drtopk.h")
 TUNING_PATH = os.path.join(HERE, "tuning.json")  # written by paper_2109_08219_amd.tune
 
-U32, F32, I32 = 0, 1, 2
+U32, F32, I32, U64, I64, F64 = 0, 1, 2, 3, 4, 5
 SMALLEST = 0x100  # OR-ed into a dtype code: the k smallest instead of the k largest
-_DTYPES = {"u32": U32, "f32": F32, "i32": I32}
+_DTYPES = {"u32": U32, "f32": F32, "i32": I32, "u64": U64, "i64": I64, "f64": F64}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error", 4: "unsupported",
           5: "workspace exceeds the no-allocation scratch buffer"}
 
@@ -157,6 +157,12 @@ def _dtype_code(t, dtype):
         return _DTYPES[dtype]
     if t.dtype == torch.float32:
         return F32
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.uint64:
+        return U64
+    if t.dtype == torch.int64:
+        return I64
     if t.dtype == torch.uint32:
         return U32
     if t.dtype == torch.int32:
@@ -168,8 +174,8 @@ def _dtype_code(t, dtype):
 def _prep(keys, dtype, largest: bool = True):
     if not keys.is_cuda:
         raise ValueError("keys must be a GPU tensor")
-    if keys.dim() != 1 or not keys.is_contiguous() or keys.element_size() != 4:
-        raise ValueError("keys must be a contiguous 1-D tensor of 4-byte elements")
+    if keys.dim() != 1 or not keys.is_contiguous() or keys.element_size() not in (4, 8):
+        raise ValueError("keys must be a contiguous 1-D tensor of 4- or 8-byte elements")
     return _dtype_code(keys, dtype) | (0 if largest else SMALLEST)
 
 
@@ -265,10 +271,11 @@ class Batch:
 
     problems: list of (keys, k), (keys, k, dtype) or (keys, k, dtype, largest) -- dtype None
     = from the tensor, largest False = the k smallest.  All outputs of problem i live in
-    three packed int32 buffers: vals[off[i] : off[i] + k_i] (bit patterns of the keys'
-    dtype), idx[same range] (uint32 positions) and kth[i].  kth_only=True asks for the
-    k-th values alone (no vals / idx buffers).  The descriptors are built once; run()
-    enqueues one topk_select_batched call on `stream`.
+    three packed int32 buffers: vals[voff[i] : voff[i] + w_i k_i] (bit patterns of the keys'
+    dtype; w_i = 1 for 4-byte and 2 for 8-byte keys, whose offsets are even),
+    idx[off[i] : off[i] + k_i] (uint32 positions) and kth[2i : 2i + w_i].  kth_only=True
+    asks for the k-th values alone (no vals / idx buffers).  The descriptors are built
+    once; run() enqueues one topk_select_batched call on `stream`.
     """
 
     def __init__(self, problems, *, kth_only: bool = False):
@@ -278,19 +285,24 @@ class Batch:
         self.ks = [int(pr[1]) for pr in problems]
         self.codes = [_prep(pr[0], pr[2] if len(pr) > 2 else None, pr[3] if len(pr) > 3 else True)
                       for pr in problems]
+        self.words = [t.element_size() // 4 for t in self.keys]
         self.kth_only = kth_only
         dev = self.keys[0].device if self.keys else torch.device("cuda")
         self.off = [0] * self.count
-        total = 0
+        self.voff = [0] * self.count
+        total = vtotal = 0
         for i, k in enumerate(self.ks):
             self.off[i] = total
             total += k
+            vtotal += vtotal % self.words[i]  # 8-byte values start at an even word
+            self.voff[i] = vtotal
+            vtotal += k * self.words[i]
         self.total_k = total
-        self.kth = torch.empty(max(1, self.count), dtype=torch.int32, device=dev)
+        self.kth = torch.empty(max(2, 2 * self.count), dtype=torch.int32, device=dev)
         if kth_only:
             self.vals = self.idx = None
         else:
-            self.vals = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+            self.vals = torch.empty(max(1, vtotal), dtype=torch.int32, device=dev)
             self.idx = torch.empty(max(1, total), dtype=torch.int32, device=dev)
         self._descs = (Problem * max(1, self.count))()
         vb = self.vals.data_ptr() if self.vals is not None else 0
@@ -299,8 +311,8 @@ class Batch:
         for i in range(self.count):
             kt = self.keys[i]
             self._descs[i] = Problem(kt.data_ptr(), kt.numel(), self.ks[i], self.codes[i],
-                                     vb + 4 * self.off[i] if vb else None,
-                                     ib + 4 * self.off[i] if ib else None, kb + 4 * i)
+                                     vb + 4 * self.voff[i] if vb else None,
+                                     ib + 4 * self.off[i] if ib else None, kb + 8 * i)
 
     def run(self, stream=None, check: bool = False) -> None:
         rc = lib().topk_select_batched(self._descs, self.count, _stream(stream))
@@ -312,13 +324,13 @@ class Batch:
         return t.view(self.keys[i].dtype)
 
     def values(self, i: int):
-        return self._as_keys(self.vals[self.off[i]:self.off[i] + self.ks[i]], i)
+        return self._as_keys(self.vals[self.voff[i]:self.voff[i] + self.words[i] * self.ks[i]], i)
 
     def indices(self, i: int):
         return self.idx[self.off[i]:self.off[i] + self.ks[i]]
 
     def kth_value(self, i: int):
-        return self._as_keys(self.kth[i:i + 1], i)
+        return self._as_keys(self.kth[2 * i:2 * i + self.words[i]], i)
 
 
 def topk_select_batched(problems, *, check: bool = False, stream=None):

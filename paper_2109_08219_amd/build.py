@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libdrtopk.so")
 CSRC = os.path.join(HERE, "csrc")
 # host API + batched kernels, the serving dispatcher, and one translation unit
 # per key codec of the single-problem path (compiled in parallel)
-SOURCES = [os.path.join(CSRC, "drtopk.hip"), os.path.join(CSRC, "server.cpp")] + sorted(
+SOURCES = [os.path.join(CSRC, "drtopk.hip"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "wide.hip")] + sorted(
     os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.startswith("codec_") and f.endswith(".hip"))
 HEADERS = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h"))
 HEADERS.append(os.path.join(ROOT, "include", "drtopk.h"))

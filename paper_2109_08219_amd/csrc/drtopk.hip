@@ -25,6 +25,7 @@
 #include "drtopk.h"
 #include "host.h"
 #include "batched.h"
+#include "wide_host.h"
 
 namespace drtopk {
 
@@ -329,7 +330,7 @@ int ensure_batch_bytes(Workspace* ws, size_t need, size_t dev_need) {
 // kernels' codec.
 bool dtype_ok(int dtype) {
   const int base = dtype & ~DRTOPK_SMALLEST;
-  return base == DRTOPK_U32 || base == DRTOPK_F32 || base == DRTOPK_I32;
+  return base == DRTOPK_U32 || base == DRTOPK_F32 || base == DRTOPK_I32 || wide_dtype(dtype);
 }
 int dt_code(int dtype) {
   const int base = dtype & ~DRTOPK_SMALLEST;
@@ -342,6 +343,7 @@ int check_args(const void* keys, uint64_t n, uint32_t k, int dtype) {
   if (n == 0 || n >= (1ull << 32)) return DRTOPK_EINVAL;
   if (k == 0 || (uint64_t)k > n) return DRTOPK_EINVAL;
   if (!dtype_ok(dtype)) return DRTOPK_EINVAL;
+  if (wide_dtype(dtype) && (reinterpret_cast<uintptr_t>(keys) & 7u) != 0) return DRTOPK_EINVAL;
   return DRTOPK_OK;
 }
 
@@ -415,6 +417,53 @@ int run_common(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_va
   return after(p, ws->ptr, s);
 }
 
+// 64-bit keys: plan, workspace and the whole path; `after(const WPlan&, void*
+// ws, hipStream_t)` runs under the workspace lock after the enqueue.
+template <typename F>
+int run_wide(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_vals, uint32_t* out_idx, void* out_kth,
+             bool kth_only, const drtopk_options_t* opt, void* stream, F&& after, bool pos_in_ws = false) {
+  int st = check_args(keys, n, k, dtype);
+  if (st) return st;
+  WPlan p;
+  const bool ws_pos = pos_in_ws && !out_idx && !kth_only;
+  st = wide_plan(n, k, dtype, (reinterpret_cast<uintptr_t>(keys) & 15u) == 0, opt, &p, ws_pos);
+  if (st) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
+  Workspace* ws = workspace_entry(dev, stream);
+  if (!ws) return DRTOPK_ENOMEM;
+  std::lock_guard<std::mutex> g(ws->mu);
+  st = ensure_record(ws);
+  if (st) return st;
+  st = ensure_bytes(ws, p.total);
+  if (st) return st;
+  if (ws_pos) out_idx = at<uint32_t>(ws->ptr, p.off_pos);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = wide_enqueue(p, keys, ws->ptr, ws->rec, out_vals, out_idx, out_kth, kth_only, s);
+  if (st) return st;
+  return after(p, ws->ptr, s);
+}
+
+int fill_stats_wide(const WPlan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
+  if (!stats) return DRTOPK_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return DRTOPK_EDEVICE;
+  uint64_t scanned = 0, cand = 0, tkey = 0;
+  uint32_t err = 0, tidx = 0;
+  if (wide_counters(p, ws, &scanned, &cand, &err, &tkey, &tidx)) return DRTOPK_EDEVICE;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->mode = p.mode;
+  stats->alpha = p.alpha;
+  stats->beta = 1;
+  stats->subranges = p.S;
+  stats->delegates = p.S;
+  stats->scanned = scanned;
+  stats->candidates = cand;
+  stats->t_key_bits = (uint32_t)(tkey >> 32);
+  stats->t_idx = tidx;
+  stats->err_flags = err;
+  return err ? DRTOPK_EDEVICE : DRTOPK_OK;
+}
+
 // Subrange exponent of a problem taken by the batched workgroup kernel; 0 =
 // sorted outright (n <= kBSmallN) or radix select without delegates.
 int batched_alpha(uint64_t n, uint32_t k) {
@@ -436,6 +485,9 @@ int batched_alpha(uint64_t n, uint32_t k) {
 }
 
 bool batched_eligible(uint64_t n, uint32_t k) { return n <= kBMaxN && k <= kBMaxK; }
+bool batched_eligible(const drtopk_problem_t& q) {
+  return batched_eligible(q.n, q.k) && !wide_dtype((int)q.dtype);
+}
 
 // Enqueues one k_batched launch over `items` (already validated).
 BatchDesc make_desc(const drtopk_problem_t& q) {
@@ -660,6 +712,9 @@ int topk_select_ex(const void* keys, uint64_t n, uint32_t k, int dtype, void* ou
                    const drtopk_options_t* opt, drtopk_stats_t* stats, void* stream) {
   if (!out_vals) return DRTOPK_EINVAL;
   try {
+    if (wide_dtype(dtype))
+      return run_wide(keys, n, k, dtype, out_vals, out_idx, nullptr, false, opt, stream,
+                      [&](const WPlan& p, void* ws, hipStream_t s) { return fill_stats_wide(p, ws, s, stats); });
     return run_common(keys, n, k, dtype, out_vals, out_idx, nullptr, false, opt, stream,
                       [&](const Plan& p, void* ws, hipStream_t s) { return fill_stats(p, ws, s, stats); });
   } catch (...) {
@@ -678,16 +733,20 @@ int topk_select_noalloc(const void* keys, uint64_t n, uint32_t k, int dtype, voi
   int st = check_args(keys, n, k, dtype);
   if (st) return st;
   try {
+    const bool wide = wide_dtype(dtype);
     Plan p;
-    st = make_plan(keys, n, k, dtype, nullptr, &p);
+    WPlan wp;
+    st = wide ? wide_plan(n, k, dtype, (reinterpret_cast<uintptr_t>(keys) & 15u) == 0, nullptr, &wp)
+              : make_plan(keys, n, k, dtype, nullptr, &p);
     if (st) return st;
-    if (p.total > kScratchBytes - kScratchRec) return DRTOPK_ESCRATCH;
+    if ((wide ? wp.total : p.total) > kScratchBytes - kScratchRec) return DRTOPK_ESCRATCH;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DRTOPK_EDEVICE;
     void* base = scratch_base(dev);
     if (!base) return DRTOPK_EDEVICE;
     void* ws = static_cast<char*>(base) + kScratchRec;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (wide) return wide_enqueue(wp, keys, ws, static_cast<uint32_t*>(base), out_vals, out_idx, nullptr, false, s);
     p.rec = static_cast<uint32_t*>(base);
     p.marks = false;  // no timing events
     return enqueue_plan(p, keys, ws, out_vals, out_idx, nullptr, false, false, s);
@@ -699,6 +758,9 @@ int topk_select_noalloc(const void* keys, uint64_t n, uint32_t k, int dtype, voi
 int kth_select(const void* keys, uint64_t n, uint32_t k, int dtype, void* out_kth, void* stream) {
   if (!out_kth) return DRTOPK_EINVAL;
   try {
+    if (wide_dtype(dtype))
+      return run_wide(keys, n, k, dtype, nullptr, nullptr, out_kth, true, nullptr, stream,
+                      [](const WPlan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
     return run_common(keys, n, k, dtype, nullptr, nullptr, out_kth, true, nullptr, stream,
                       [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
   } catch (...) {
@@ -720,7 +782,7 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
     // problems a workgroup can own go to one persistent launch, largest first
     std::vector<const drtopk_problem_t*> small, large;
     for (uint32_t i = 0; i < count; ++i)
-      (batched_eligible(problems[i].n, problems[i].k) ? small : large).push_back(&problems[i]);
+      (batched_eligible(problems[i]) ? small : large).push_back(&problems[i]);
     std::stable_sort(small.begin(), small.end(),
                      [](const drtopk_problem_t* a, const drtopk_problem_t* b) { return a->n > b->n; });
     if (!small.empty()) {
@@ -735,8 +797,12 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
       if (st) return st;
     }
     for (const drtopk_problem_t* q : large) {
-      int st = run_common(q->keys, q->n, q->k, (int)q->dtype, q->out_vals, q->out_idx, q->out_kth, !q->out_vals,
-                          nullptr, stream, [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
+      const int st =
+          wide_dtype((int)q->dtype)
+              ? run_wide(q->keys, q->n, q->k, (int)q->dtype, q->out_vals, q->out_idx, q->out_kth, !q->out_vals,
+                         nullptr, stream, [](const WPlan&, void*, hipStream_t) { return (int)DRTOPK_OK; })
+              : run_common(q->keys, q->n, q->k, (int)q->dtype, q->out_vals, q->out_idx, q->out_kth, !q->out_vals,
+                           nullptr, stream, [](const Plan&, void*, hipStream_t) { return (int)DRTOPK_OK; });
       if (st) return st;
     }
   } catch (...) {
@@ -750,6 +816,13 @@ int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes) {
   alignas(16) static const uint32_t dummy[4] = {0, 0, 0, 0};
   int st = check_args(dummy, n, k, dtype);
   if (st) return st;
+  if (wide_dtype(dtype)) {
+    WPlan wp;
+    st = wide_plan(n, k, dtype, true, nullptr, &wp);
+    if (st) return st;
+    *bytes = 8 * n + 12ull * k + 8 + wp.total;
+    return DRTOPK_OK;
+  }
   uint64_t ws = sizeof(BatchDesc);
   if (!batched_eligible(n, k)) {
     Plan p;
@@ -805,6 +878,7 @@ int drtopk_delegates(const void* keys, uint64_t n, int dtype, int alpha, int bet
   if (!out_dkeys || !out_didx) return DRTOPK_EINVAL;
   int st = check_args(keys, n, 1, dtype);
   if (st) return st;
+  if (wide_dtype(dtype)) return DRTOPK_EUNSUPPORTED;
   if (alpha < 0 || alpha > 24 || !valid_beta(beta)) return DRTOPK_EINVAL;
   drtopk_options_t o{alpha, beta, 1, 0};
   Plan p;
@@ -834,6 +908,7 @@ int drtopk_candidates(const void* keys, uint64_t n, uint32_t k, int dtype, int a
                       uint32_t* out_pos, uint64_t cap, uint64_t* count, uint32_t* t_out, void* stream) {
   if (!out_pos || !count) return DRTOPK_EINVAL;
   if (alpha < 0 || alpha > 24 || !valid_beta(beta)) return DRTOPK_EINVAL;
+  if (wide_dtype(dtype)) return dtype_ok(dtype) ? DRTOPK_EUNSUPPORTED : DRTOPK_EINVAL;
   drtopk_options_t o{alpha, beta, 1, variant};
   try {
     return run_common(keys, n, k, dtype, nullptr, nullptr, nullptr, true, &o, stream,
@@ -868,6 +943,16 @@ int drtopk_plan(uint64_t n, uint32_t k, int dtype, drtopk_options_t* out) {
   static const uint32_t dummy[4] = {0, 0, 0, 0};
   int st = check_args(dummy, n, k, dtype);
   if (st) return st;
+  if (wide_dtype(dtype)) {
+    WPlan wp;
+    st = wide_plan(n, k, dtype, true, nullptr, &wp);
+    if (st) return st;
+    out->alpha = wp.alpha;
+    out->beta = 1;
+    out->mode = wp.mode;
+    out->variant = 0;
+    return DRTOPK_OK;
+  }
   Plan p;
   st = make_plan(dummy, n, k, dtype, nullptr, &p);
   if (st) return st;
@@ -964,21 +1049,22 @@ int topk_select_payload(const void* keys, uint64_t n, uint32_t k, int dtype, con
     // the gather is enqueued under the workspace lock, so with out_idx NULL it
     // reads the positions from the workspace before any later call on the
     // stream can overwrite them
+    auto gather = [&](size_t off_pos, void* ws, hipStream_t s) {
+      const uint32_t* idx = out_idx ? out_idx : at<uint32_t>(ws, off_pos);
+      const unsigned g = grid_for(k, 256, 1024);
+      if (payload_bytes == 4)
+        hipLaunchKernelGGL(k_gather_payload<uint32_t>, dim3(g), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(payload), idx, k, static_cast<uint32_t*>(out_payload));
+      else
+        hipLaunchKernelGGL(k_gather_payload<uint64_t>, dim3(g), dim3(256), 0, s,
+                           static_cast<const uint64_t*>(payload), idx, k, static_cast<uint64_t*>(out_payload));
+      return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
+    };
+    if (wide_dtype(dtype))
+      return run_wide(keys, n, k, dtype, out_vals, out_idx, nullptr, false, nullptr, stream,
+                      [&](const WPlan& p, void* ws, hipStream_t s) { return gather(p.off_pos, ws, s); }, true);
     return run_common(keys, n, k, dtype, out_vals, out_idx, nullptr, false, nullptr, stream,
-                      [&](const Plan& p, void* ws, hipStream_t s) {
-                        const uint32_t* idx = out_idx ? out_idx : at<uint32_t>(ws, p.off_pos);
-                        const unsigned g = grid_for(k, 256, 1024);
-                        if (payload_bytes == 4)
-                          hipLaunchKernelGGL(k_gather_payload<uint32_t>, dim3(g), dim3(256), 0, s,
-                                             static_cast<const uint32_t*>(payload), idx, k,
-                                             static_cast<uint32_t*>(out_payload));
-                        else
-                          hipLaunchKernelGGL(k_gather_payload<uint64_t>, dim3(g), dim3(256), 0, s,
-                                             static_cast<const uint64_t*>(payload), idx, k,
-                                             static_cast<uint64_t*>(out_payload));
-                        return hipGetLastError() == hipSuccess ? (int)DRTOPK_OK : (int)DRTOPK_EDEVICE;
-                      },
-                      false, true);
+                      [&](const Plan& p, void* ws, hipStream_t s) { return gather(p.off_pos, ws, s); }, false, true);
   } catch (...) {
     return DRTOPK_EDEVICE;
   }
@@ -989,6 +1075,7 @@ int topk_select_host(const void* host_keys, uint64_t n, uint32_t k, int dtype, u
   if (!out_vals) return DRTOPK_EINVAL;
   int st = check_args(host_keys, n, k, dtype);
   if (st) return st;
+  if (wide_dtype(dtype)) return DRTOPK_EUNSUPPORTED;
   if (chunk == 0) chunk = n < (1ull << 26) ? n : (1ull << 26);
   if (chunk > n) return DRTOPK_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

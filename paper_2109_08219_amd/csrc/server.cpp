@@ -285,7 +285,9 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
   Req r;
   r.p = *req;
   r.fp = fp;
-  r.large = route == 0;
+  // 64-bit keys always take the single-problem path (the batched kernel is 32-bit)
+  const int base = (int)(req->dtype & ~(uint32_t)DRTOPK_SMALLEST);
+  r.large = route == 0 || base == DRTOPK_U64 || base == DRTOPK_I64 || base == DRTOPK_F64;
   r.arrival = arrival;
   {
     std::lock_guard<std::mutex> g(s->mu);

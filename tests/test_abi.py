@@ -66,12 +66,41 @@ def test_dtype_codes_without_gpu():
     """int32 keys and the k-smallest flag are valid with every key type; other codes are not."""
     L = drt.lib()
     o = drt.Options()
-    for code in (0, 1, 2, 0x100, 0x101, 0x102):
+    for code in (0, 1, 2, 3, 4, 5, 0x100, 0x101, 0x102, 0x103, 0x104, 0x105):
         assert L.drtopk_plan(1 << 20, 100, code, ctypes.byref(o)) == 0, code
-    for code in (3, 4, 0x103, 0x200, 0x300, -1):
+    for code in (6, 7, 0x106, 0x200, 0x300, -1):
         assert L.drtopk_plan(1 << 20, 100, code, ctypes.byref(o)) == 1, code
     assert drt.plan(1 << 20, 100, "i32-min") == drt.plan(1 << 20, 100, "u32")
     assert drt.footprint(1 << 24, 1000, "f32-min") == drt.footprint(1 << 24, 1000, "f32")
+
+
+def test_wide_keys_without_gpu():
+    """64-bit keys: planned with one delegate per subrange of at least 128 keys or the
+    plain radix select; 8-byte alignment required; beta > 1, the delegate and
+    candidate stage calls and host streaming refused before any device work."""
+    L = drt.lib()
+    o = drt.Options()
+    for code in (drt.U64, drt.I64, drt.F64, drt.F64 | drt.SMALLEST):
+        assert L.drtopk_plan(1 << 28, 1024, code, ctypes.byref(o)) == 0
+        assert (o.mode, o.beta) == (1, 1) and 7 <= o.alpha <= 13, (o.mode, o.alpha, o.beta)
+        assert L.drtopk_plan(1 << 20, 100000, code, ctypes.byref(o)) == 0 and o.mode == 2  # k > n/16
+        assert L.drtopk_plan(5000, 10, code, ctypes.byref(o)) == 0 and o.mode == 2  # small input
+    d16, d12, out = ctypes.c_void_p(16), ctypes.c_void_p(12), ctypes.c_void_p(32)
+    assert L.topk_select(d12, 1000, 5, drt.U64, out, None, None) == 1  # keys not 8-byte aligned
+    assert L.kth_select(d12, 1000, 5, drt.F64, out, None) == 1
+    opt = drt.Options(-1, 2, 1, 0)
+    assert L.topk_select_ex(d16, 1 << 20, 100, drt.I64, out, None, ctypes.byref(opt), None, None) == 4  # beta 2
+    opt = drt.Options(5, 1, 1, 0)
+    assert L.topk_select_ex(d16, 1 << 20, 100, drt.I64, out, None, ctypes.byref(opt), None, None) == 1  # alpha < 7
+    opt = drt.Options(-1, 0, 3, 0)
+    assert L.topk_select_ex(d16, 1 << 12, 100, drt.I64, out, None, ctypes.byref(opt), None, None) == 4  # one workgroup
+    assert L.drtopk_delegates(d16, 1 << 20, drt.U64, 8, 1, out, out, None) == 4
+    host = (ctypes.c_uint64 * 16)()
+    assert L.topk_select_host(host, 16, 1, drt.U64, 0, out, None, None) == 4
+    # footprint: 8-byte keys and values, 4-byte positions, plus the workspace
+    f64 = drt.footprint(1 << 24, 1000, "f64")
+    assert f64 > 8 * (1 << 24) + 12 * 1000
+    assert drt.footprint(1 << 24, 1000, "u64") == f64
 
 
 def test_payload_arguments_without_gpu():
@@ -107,7 +136,7 @@ def test_host_stream_arguments_without_gpu():
     assert L.topk_select_host(host, 16, 1, 0, 0, None, None, None) == 1  # no output
     assert L.topk_select_host(host, 16, 17, 0, 0, out, None, None) == 1  # k > n
     assert L.topk_select_host(host, 16, 1, 0, 17, out, None, None) == 1  # chunk > n
-    assert L.topk_select_host(host, 16, 1, 3, 0, out, None, None) == 1  # not a key type
+    assert L.topk_select_host(host, 16, 1, 6, 0, out, None, None) == 1  # not a key type
 
 
 def test_null_pointers_rejected():

@@ -6,6 +6,7 @@ sorted and heavy-duplicate stand-ins; the full-size cases run the planner's
 choice at N = 2^30 (and 2^29 for the adversarial inputs) and are checked by
 invariants that fix the answer uniquely.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -236,12 +237,16 @@ def test_errors_on_gpu():
         drt.topk_select(t, 0)
     with pytest.raises(drt.DrTopkError):
         drt.topk_select(t, 101)
-    with pytest.raises(ValueError):
-        drt.topk_select(t.to(torch.float64), 3)
+    with pytest.raises(ValueError):  # 2-byte elements
+        drt.topk_select(t.to(torch.float16), 3)
     with pytest.raises(KeyError):  # not a key type
-        drt.topk_select(t, 3, dtype="u64")
+        drt.topk_select(t, 3, dtype="u16")
     with pytest.raises(ValueError):
         drt.topk_select(t.cpu(), 3)
+    # 64-bit keys at an address that is not 8-byte aligned: refused before any work
+    out = torch.empty(4, dtype=torch.int64, device="cuda")
+    assert drt.lib().topk_select(ctypes.c_void_p(t.data_ptr() + 4), 25, 3, drt.U64, ctypes.c_void_p(out.data_ptr()),
+                                 None, None) == 1
 
 
 # ---------------------------------------------------------------------------
