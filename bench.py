@@ -228,6 +228,30 @@ def bench_delegates_vs_plain(drt, torch, t_u):
     return out
 
 
+def bench_inner_by_k(drt, torch, t_u):
+    """The top-k algorithm the delegates assist, by k (the paper's choice of
+    algorithm as k grows, Sections 5.1 and 6.1): N = 2^28 uint32 uniform, the
+    planner's alpha and beta, with the fused one-kernel tail (variant 0, the
+    default), MSD radix selects (1), the bitonic top-k (2, k <= 256) and
+    bucket selects (3) for the first and second top-k; k = 2^0 .. 2^20."""
+    t = t_u[: 1 << 28]
+    names = {0: "fused", 1: "radix", 2: "bitonic", 3: "bucket"}
+    out = []
+    for lg_k in (0, 2, 4, 6, 8, 10, 12, 14, 16, 18, 20):
+        k = 1 << lg_k
+        v = torch.empty(k, dtype=t.dtype, device="cuda")
+        ix = torch.empty(k, dtype=torch.int32, device="cuda")
+        row = {"k": k}
+        for variant, name in names.items():
+            if variant == 2 and k > 256:
+                continue
+            r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix, mode=1, variant=variant), 5, 1)
+            row[name + "_ms"] = r["ms_median"]
+        row["best"] = min((row[n + "_ms"], n) for n in names.values() if n + "_ms" in row)[1]
+        out.append(row)
+    return out
+
+
 def bench_adversarial(drt, torch, args):
     """N = 2^29, k = 16384: float32 N(0,1) sorted ascending (beta 1, 2, 4, 8) and uint32
     uniform over [0, 16) (planner's choice).  Inputs drawn on the GPU."""
@@ -305,7 +329,8 @@ def main() -> int:
     ap.add_argument("--no-smallest", action="store_true", help="skip the k smallest / int32 cases")
     ap.add_argument("--no-host", action="store_true", help="skip top-k of keys in host memory")
     ap.add_argument("--no-by-k", action="store_true",
-                    help="skip delegates against the plain radix select and the 2^27 shard cases")
+                    help="skip the by-k studies (delegates against the plain radix select, the inner "
+                         "top-k algorithm) and the 2^27 shard cases")
     ap.add_argument("--delegate-vector", default=None, metavar="A:B,...",
                     help="only build the delegate vector for these (alpha, beta) pairs (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -461,6 +486,7 @@ def main() -> int:
     del cases
     smallest_i32 = None if args.no_smallest else bench_smallest_i32(drt, torch, t_u, t_f)
     by_k = None if args.no_by_k else bench_delegates_vs_plain(drt, torch, t_u)
+    inner_by_k = None if args.no_by_k else bench_inner_by_k(drt, torch, t_u)
     shard = None if args.no_by_k else bench_shard(drt, torch, t_u, t_f)
     del t_u, t_f
     torch.cuda.empty_cache()
@@ -497,6 +523,7 @@ def main() -> int:
         "small_case": small,
         "smallest_and_i32": smallest_i32,
         "delegates_vs_plain_radix": by_k,
+        "inner_by_k": inner_by_k,
         "shard_2p27": shard,
         "host_stream": host_stream,
         "adversarial": adversarial,

@@ -174,9 +174,14 @@ int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha)
  *          over V with no delegates, 3 = the whole problem in one workgroup
  *          (the batched form's kernel, one launch; n <= 2^22, k <= 2048; the
  *          planner takes it for n <= 2^16; alpha is then the batched form's)
- *   variant  implementation of the steps after the delegate pass: 0 = one
- *          cooperative kernel (default), 1 = one kernel per step.  Both give
- *          bit-identical results. */
+ *   variant  implementation of the steps after the delegate pass, i.e. the
+ *          top-k algorithm the delegates assist (Sections 5.1 and 6.1):
+ *          0 = one cooperative kernel (default: histogram cut, survivors
+ *          bucketed and sorted), 1 = one kernel per step with MSD radix
+ *          selects, 2 = bitonic top-k for both selections (k <= 256, else
+ *          DRTOPK_EINVAL), 3 = bucket select (equal-width buckets over the
+ *          live min..max range) for both selections.  All give bit-identical
+ *          results; 32-bit keys only (64-bit keys take 0 or 1, same path). */
 typedef struct {
   int32_t alpha;
   int32_t beta;

@@ -116,7 +116,8 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
   if (mode == 3) p.alpha = batched_alpha(n, k);
   p.mode = mode;
   p.variant = opt ? opt->variant : 0;
-  if (p.variant < 0 || p.variant > 1) return DRTOPK_EINVAL;
+  if (p.variant < 0 || p.variant > 3) return DRTOPK_EINVAL;
+  if (p.variant == 2 && k > kBtMaxK) return DRTOPK_EINVAL;  // the bitonic top-k holds k <= 256
   if (mode == 1) {
     int ta = -1, tb = 0;
     if (!tune_lookup(DRTOPK_FORM_SINGLE, n, k, &ta, &tb)) ta = -1, tb = 0;
@@ -182,6 +183,10 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
       p.off_skey = seg(p.cap_c * 4);  // survivors scattered into output-bucket order
       p.off_sidx = seg(p.cap_c * 4);
     }
+  }
+  if (mode == 1 && p.variant == 2) {  // partial lists of the bitonic rounds
+    p.off_L0 = seg((size_t)kBtRoundBlocks * kBtMaxK * 8);
+    p.off_L1 = seg((size_t)kBtRoundBlocks * kBtMaxK * 8);
   }
   if (pos_in_ws) p.off_pos = seg((size_t)k * 4);
   p.off_okey = seg((size_t)k * 4);

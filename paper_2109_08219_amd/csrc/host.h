@@ -26,12 +26,14 @@ struct Plan {
   uint64_t S = 0, nd = 0, cap_c = 0, chunk = 0, M = 0;
   uint32_t kD = 0;   // rank sought among the delegates: min(k, |D|)
   uint32_t slack = 0;
-  int variant = 0;   // 0: cooperative tail kernel, 1: one kernel per step
+  int variant = 0;   // 0: cooperative tail kernel, 1: one kernel per step (radix selects),
+                     // 2: bitonic top-k selects (k <= 256), 3: bucket selects
   bool all = false;  // fewer real delegates than k: no threshold, every subrange qualifies
   bool vec = false;
   size_t off_ctl = 0, off_dkey = 0, off_didx = 0, off_q = 0, off_ckey = 0, off_cidx = 0;
   size_t off_okey = 0, off_oidx = 0, off_A = 0, off_B = 0, off_skey = 0, off_sidx = 0, total = 0;
   size_t off_pos = 0;  // k output positions kept in the workspace (payload gathers without out_idx)
+  size_t off_L0 = 0, off_L1 = 0;  // variant 2: partial top-k lists of the bitonic rounds
   uint32_t* rec = nullptr;  // the stream's check record (set by the caller before the enqueue)
   bool marks = true;        // phase timing events may be recorded (drtopk_timing_enable)
 };

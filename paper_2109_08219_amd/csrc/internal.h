@@ -21,6 +21,8 @@ constexpr int kBins = 2048;       // 11-bit radix digits
 constexpr int kPasses = 6;        // 64-bit composite = 11+11+10 key bits, 11+11+10 position bits
 constexpr int kSmallCap = 8192;   // candidate counts sorted by one workgroup in LDS
 constexpr int kSortTile = 4096;   // block-sort tile of the large-k output sort
+constexpr uint32_t kBtMaxK = 256;        // largest k of the bitonic top-k (tail variant 2)
+constexpr uint32_t kBtRoundBlocks = 256; // most blocks of one bitonic top-k round
 
 // Key codecs: bits 0-1 the key type, DT_MIN set = the k smallest first.
 enum { DT_U32 = 0, DT_F32 = 1, DT_I32 = 2, DT_MIN = 4 };
@@ -82,6 +84,13 @@ struct Ctl {
   uint32_t tpub[2];   // threshold t published by block 0 of the tail (coherent stores)
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
   uint64_t max1;  // largest delegate composite = largest element (the k = 1 answer)
+  // bucket select (tail variant 3), [0] over the delegates, [1] over the survivors
+  uint64_t bmax[2];   // largest composite of the source
+  uint64_t bnmin[2];  // complement of the smallest
+  uint64_t blo[2], bhi[2];  // live range, shrunk to the bucket holding the sought rank
+  uint32_t brank[2];  // rank still sought inside it
+  uint32_t bdone[2];  // the range is one composite: the selection is done
+  uint32_t bticket[2][kPasses];  // its pass tickets (histograms: histW over the delegates, histC)
   uint32_t nq;    // subranges to re-read
   uint32_t nc;    // survivors
   uint32_t nout;  // compacted outputs (large-survivor path)

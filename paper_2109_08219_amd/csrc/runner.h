@@ -4,6 +4,7 @@
 #pragma once
 
 #include "host.h"
+#include "inner.h"
 #include "kernels.h"
 #include "tail.h"
 
@@ -102,6 +103,98 @@ struct Runner {
     }
   }
 
+  // Rounds of the bitonic top-k over `key`/`idx` (SRC_D or SRC_C, at most
+  // `bound` entries) down to one block, which finishes with `fin` (1: the
+  // threshold t, 2: the sorted outputs).  Each round's blocks fold tiles of
+  // 4096 into one list of K = 2^ceil(log2 k) entries.
+  template <int SRC>
+  static void bitonic(const Plan& p, const uint32_t* key, const uint32_t* idx, uint64_t bound, int fin, Ctl* ctl,
+                      void* ws, uint32_t* out_vals, uint32_t* out_idx, uint32_t* out_kth, hipStream_t st) {
+    uint32_t K = 1;
+    while (K < p.k) K <<= 1;
+    uint64_t* cur = at<uint64_t>(ws, p.off_L0);
+    uint64_t* nxt = at<uint64_t>(ws, p.off_L1);
+    const auto blocks = [](uint64_t entries) {
+      const uint64_t t = (entries + kBtTile - 1) / kBtTile;
+      return (unsigned)(t < 1 ? 1 : t > kBtRoundBlocks ? kBtRoundBlocks : t);
+    };
+    unsigned g = blocks(bound);
+    hipLaunchKernelGGL((k_btopk<SRC, DT>), dim3(g), dim3(kBtThreads), 0, st, key, idx, (const uint64_t*)nullptr,
+                       bound, K, g == 1 ? fin : 0, p.k, ctl, cur, out_vals, out_idx, out_kth);
+    uint64_t cnt = (uint64_t)g * K;
+    while (g > 1) {
+      g = blocks(cnt);
+      hipLaunchKernelGGL((k_btopk<SRC_OUT, DT>), dim3(g), dim3(kBtThreads), 0, st, (const uint32_t*)nullptr,
+                         (const uint32_t*)nullptr, cur, cnt, K, g == 1 ? fin : 0, p.k, ctl, nxt, out_vals, out_idx,
+                         out_kth);
+      cnt = (uint64_t)g * K;
+      std::swap(cur, nxt);
+    }
+  }
+
+  // Bucket select over `key`/`idx`: min/max, then at most kPasses passes that
+  // each keep the bucket holding rank k; the result lands in selD (which 0)
+  // or selC (which 1).
+  template <int SRC>
+  static void bucket(const Plan& p, const uint32_t* key, const uint32_t* idx, uint64_t bound, int which, Ctl* ctl,
+                     hipStream_t st) {
+    const unsigned g = grid_for(bound, 256 * 8, 1024);
+    hipLaunchKernelGGL((k_bminmax<SRC, DT>), dim3(g), dim3(256), 0, st, key, idx, bound, which, ctl);
+    for (int pass = 0; pass < kPasses; ++pass)
+      hipLaunchKernelGGL((k_bpass<SRC, DT>), dim3(g), dim3(256), 0, st, key, idx, bound, pass, which, p.k, ctl);
+  }
+
+  // The delegate method with the bitonic top-k (variant 2) or the bucket
+  // select (variant 3) as both of its selections; Rule 3 and the re-read are
+  // variant 1's kernels.
+  static void run_alt(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
+                      uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st, PhaseMarks& pm) {
+    Ctl* ctl = at<Ctl>(ws, p.off_ctl);
+    uint32_t* dkey = at<uint32_t>(ws, p.off_dkey);
+    uint32_t* didx = at<uint32_t>(ws, p.off_didx);
+    uint32_t* Q = at<uint32_t>(ws, p.off_q);
+    uint32_t* ckey = at<uint32_t>(ws, p.off_ckey);
+    uint32_t* cidx = at<uint32_t>(ws, p.off_cidx);
+    const uint32_t k = p.k;
+    delegate(p, keys, dkey, didx, ctl, st);
+    pm.mid(st);
+    // first top-k: t = the k-th delegate (none when fewer than k are real)
+    if (!p.all) {
+      if (p.variant == 2)
+        bitonic<SRC_D>(p, dkey, didx, p.nd, 1, ctl, ws, nullptr, nullptr, nullptr, st);
+      else
+        bucket<SRC_D>(p, dkey, didx, p.nd, 0, ctl, st);
+    }
+    qualify(p, dkey, didx, ctl, Q, ckey, cidx, st);
+    const unsigned gS = grid_for(((uint64_t)((k - 1) / p.beta) + 1) << p.alpha, 4096, 2048);
+    if (p.vec)
+      hipLaunchKernelGGL((k_scan<DT, true>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
+    else
+      hipLaunchKernelGGL((k_scan<DT, false>), dim3(gS), dim3(256), 0, st, keys, p.n, p.alpha, ctl, Q, ckey, cidx);
+    if (filter_only) return;
+    // second top-k over the survivors
+    if (p.variant == 2) {
+      bitonic<SRC_C>(p, ckey, cidx, p.cap_c, 2, ctl, ws, kth_only ? nullptr : out_vals, kth_only ? nullptr : out_idx,
+                     out_kth, st);
+      return;
+    }
+    bucket<SRC_C>(p, ckey, cidx, p.cap_c, 1, ctl, st);
+    if (kth_only) {
+      hipLaunchKernelGGL((k_kth_from_sel<DT>), dim3(1), dim3(64), 0, st, 0, ctl, out_kth);
+      return;
+    }
+    uint32_t* okey = at<uint32_t>(ws, p.off_okey);
+    uint32_t* oidx = at<uint32_t>(ws, p.off_oidx);
+    const unsigned gC = grid_for(p.cap_c, 256 * 8, 1024);
+    hipLaunchKernelGGL((k_compact<SRC_C, DT>), dim3(gC), dim3(256), 0, st, ckey, cidx, (uint64_t)0, 0, k, ctl, okey,
+                       oidx);
+    if (k <= (uint32_t)kSmallCap)
+      hipLaunchKernelGGL((k_final_small<SRC_OUT, DT>), dim3(1), dim3(1024), 0, st, okey, oidx, (uint64_t)k, 0, k, ctl,
+                         out_vals, out_idx, out_kth);
+    else
+      big_sort(p, ws, out_vals, out_idx, out_kth, 0, ctl, st);
+  }
+
   // filter_only: stop once the survivors are known (stage checks).
   static void run(const Plan& p, const uint32_t* keys, void* ws, uint32_t* out_vals, uint32_t* out_idx,
                   uint32_t* out_kth, bool kth_only, bool filter_only, hipStream_t st) {
@@ -160,6 +253,10 @@ struct Runner {
       launch_tail(p, ta, st);
       // the merge sort runs only if the tail fell back to its select path
       if (ta.big_sort && !filter_only) big_sort(p, ws, out_vals, out_idx, out_kth, 1, ctl, st);
+      return;
+    }
+    if (p.mode == 1 && p.variant >= 2) {
+      run_alt(p, keys, ws, out_vals, out_idx, out_kth, kth_only, filter_only, st, pm);
       return;
     }
     if (p.mode == 1) {
