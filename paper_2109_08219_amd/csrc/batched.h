@@ -26,6 +26,7 @@ constexpr int kBT = 512;                  // threads per workgroup (two workgrou
 constexpr int kBWaves = kBT / 64;
 constexpr uint32_t kBSmallN = 4096;       // problems this small are selected in LDS directly
 constexpr uint32_t kBMaxS = 4096;         // delegate vector capacity (LDS)
+constexpr uint32_t kBMaxSG = 16384;       // delegate vector of a split problem (global memory)
 constexpr uint32_t kBSurv = 4096;         // survivor capacity (LDS)
 constexpr uint32_t kBMaxK = 2048;         // largest k handled in a workgroup
 constexpr uint64_t kBMaxN = 1ull << 22;   // largest n handled in a workgroup
@@ -415,15 +416,19 @@ __device__ __forceinline__ void b_delegates_tail(const BatchDesc& d, uint32_t n4
   }
 }
 
-// Delegate vector for subranges of 4..128 keys: each 256-key wave-load holds
+// Delegate vector for subranges of 4..128 keys, over the keys
+// [lo, min(hi, n4)) (lo a multiple of kBStep): each 256-key wave-load holds
 // whole subranges, 2^(alpha-2) lanes each; a segmented butterfly gives each
-// subrange's maximum to its first lane.
+// subrange's maximum to its first lane, which stores it as
+// sm.D[s - lo / 2^alpha].
 template <bool VEC>
-__device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint32_t alpha, Codec cx,
-                                          BatchSmem& sm) {
+__device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4,
+                                          uint32_t alpha, Codec cx, BatchSmem& sm) {
   const uint32_t G = 1u << (alpha - 2);  // lanes per subrange
+  const uint32_t end = hi < n4 ? hi : n4;
+  const uint32_t s0 = lo >> alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t base = wave * kBStep; base < n4; base += kBWaves * kBStep) {
+  for (uint32_t base = lo + wave * kBStep; base < end; base += kBWaves * kBStep) {
     uint32_t v[kBU][4];
 #pragma unroll
     for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
@@ -434,10 +439,11 @@ __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t n4, uint
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint64_t x = comp(cx.enc(v[j][c]), p + c);
-        if (p + c < n4 && x > m) m = x;
+        if (p + c < end && x > m) m = x;
       }
       m = group_max64(m, G);
-      if ((lane & (G - 1)) == 0 && p < n4) atomicMax((unsigned long long*)&sm.D[p >> alpha], (unsigned long long)m);
+      if ((lane & (G - 1)) == 0 && p < end)
+        atomicMax((unsigned long long*)&sm.D[(p >> alpha) - s0], (unsigned long long)m);
     }
   }
 }
@@ -474,21 +480,22 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
   }
 }
 
-// Everything after the delegate vector (complete in sm.D[0..S)): t, the
-// qualifying subranges, the survivors and the output.  False if the survivors
-// overflow LDS (nothing has been written then).
+// Everything after the delegate vector: t, the qualifying subranges, the
+// survivors and the output.  sm.D[0..cnt) holds every delegate ranked at or
+// above the k-th (the whole vector, or its top part when a split problem's
+// vector lives in global memory), and sm.tail_del the delegate of the
+// subrange holding the last n mod 4 keys.  False if the survivors overflow
+// LDS (nothing has been written then).
 template <bool VEC>
-__device__ inline bool b_finish(const BatchDesc& d, BatchSmem& sm) {
+__device__ inline bool b_finish(const BatchDesc& d, uint32_t cnt, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, n4 = vec_end<VEC>(n);
-  const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
   const Keys<VEC> ks(d.keys, n4);
-  if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[n4 >> alpha] : 0;
-  const uint64_t t = lds_select(sm.D, S, k, sm);  // Rule 2: the k-th delegate
+  const uint64_t t = lds_select(sm.D, cnt, k, sm);  // Rule 2: the k-th delegate
   // the k-1 subranges whose delegate ranks above t (order irrelevant)
   uint32_t* Q = sm.hist;
   if (threadIdx.x == 0) { sm.nq = 0; sm.nsurv = 1; sm.surv[0] = t; }  // t itself: its subrange is not re-read
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < S; i += kBT) {
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBT) {
     const uint64_t x = sm.D[i];
     if (x > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(x) >> alpha;
   }
@@ -520,14 +527,56 @@ __device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
   for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
   __syncthreads();
   if (alpha >= 8) b_delegates_wide<VEC>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
-  else b_delegates_narrow<VEC>(ks, n4, alpha, codec_of(d.dtype), sm);
+  else b_delegates_narrow<VEC>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
   b_delegates_tail(d, n4, 0, sm);
   __syncthreads();
-  return b_finish<VEC>(d, sm);
+  if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[n4 >> alpha] : 0;
+  return b_finish<VEC>(d, S, sm);
 }
 
-__device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// A split problem's delegate vector (S entries, global memory, written by the
+// tiles' workgroups with coherent stores) cut down to LDS: MSD digits of the
+// composites are histogrammed over it until the class holding the k-th
+// delegate plus everything ranked above the class fit sm.D (kBMaxS), then
+// those are copied there (the k-th delegate and all delegates above it among
+// them).  Returns their count, or 0 if no cut fits (massive ties).
+__device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t k, BatchSmem& sm) {
+  uint64_t prefix = 0, mask = 0;
+  uint32_t r = k, above = 0, cls = 0;
+  bool fits = false;
+  for (int p = 0; p < kPasses; ++p) {
+    for (int i = threadIdx.x; i < kBins; i += kBT) sm.hist[i] = 0;
+    __syncthreads();
+    const int sh = pass_shift(p);
+    const uint32_t dm = (1u << pass_bits(p)) - 1;
+    for (uint32_t i = threadIdx.x; i < S; i += kBT) {
+      const uint64_t x = ld_coh64(&Dg[i]);
+      if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
+    }
+    __syncthreads();
+    bb_bucket(sm.hist, r, sm);
+    prefix |= (uint64_t)sm.out[0] << sh;
+    mask |= (uint64_t)dm << sh;
+    above += r - sm.out[1];
+    r = sm.out[1];
+    cls = sm.out[3];
+    __syncthreads();
+    if (above + cls <= kBMaxS) {
+      fits = true;
+      break;
+    }
+  }
+  if (!fits) return 0;
+  if (threadIdx.x == 0) sm.nq = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < S; i += kBT) {
+    const uint64_t x = ld_coh64(&Dg[i]);
+    if ((x & mask) >= prefix) sm.D[atomicAdd(&sm.nq, 1u)] = x;  // above + cls entries
+  }
+  __syncthreads();
+  const uint32_t cnt = sm.nq;
+  __syncthreads();
+  return cnt;
 }
 
 // Tile `tile` of a split problem (alpha >= 8): this workgroup builds the
@@ -565,7 +614,8 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   const Keys<VEC> ks(d.keys, n4);
   for (uint32_t i = threadIdx.x; i < ns; i += kBT) sm.D[i] = 0;
   __syncthreads();
-  b_delegates_wide<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
+  if (alpha >= 8) b_delegates_wide<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
+  else b_delegates_narrow<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
   if (hi == n) b_delegates_tail(d, n4, s0, sm);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < ns; i += kBT) st_coh64(&Dg[d.doff + s0 + i], sm.D[i]);
@@ -575,9 +625,15 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   __syncthreads();
   if (!sm.item) return;
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
-  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
-  __syncthreads();
-  if (b_finish<VEC>(d, sm)) return;
+  if (threadIdx.x == 0) sm.tail_del = n4 < n ? ld_coh64(&Dg[d.doff + (n4 >> alpha)]) : 0;
+  uint32_t cnt = S;
+  if (S <= kBMaxS) {
+    for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
+    __syncthreads();
+  } else {
+    cnt = b_cut_global(Dg + d.doff, S, d.k, sm);
+  }
+  if (cnt && b_finish<VEC>(d, cnt, sm)) return;
   __syncthreads();
   b_radix<VEC>(d, sm, rec);
 }

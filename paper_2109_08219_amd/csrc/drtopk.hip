@@ -476,6 +476,18 @@ int batched_alpha(uint64_t n, uint32_t k) {
   auto subranges = [n](int a) { return (n + (1ull << a) - 1) >> a; };
   int a = -1, b = 0;
   if (tune_lookup(DRTOPK_FORM_BATCHED, n, k, &a, &b) && a == 0) return 0;  // measured: radix select
+  if (n > (1ull << kBTileLog)) {
+    // split across workgroups: the delegate vector lives in global memory, so
+    // it may hold up to kBMaxSG entries and Rule 4's shorter subranges apply
+    // (at least 64 keys: a tile's delegates still fit its workgroup's LDS);
+    // fewer subranges re-read at the same k
+    if (a < 0) a = rule_alpha(n, k);
+    if (a < 6) a = 6;
+    if (a > 24) a = 24;
+    while (a < 24 && subranges(a) > kBMaxSG) ++a;
+    while (subranges(a) < 2ull * k && a > 6) --a;
+    return subranges(a) > k ? a : 0;
+  }
   if (a < 0) {
     a = rule_alpha(n, k);
     if (a < 8) a = 8;  // a wave reads 256 keys per step: shorter subranges idle lanes
@@ -509,10 +521,10 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
 }
 
 // Tiles of a problem's delegate vector (one workgroup each): problems of
-// more than 2^kBTileLog keys on the delegate route with subranges of at
-// least 256 keys are split so several workgroups stream them.
+// more than 2^kBTileLog keys on the delegate route are split so several
+// workgroups stream them (their subranges hold at least 64 keys).
 uint32_t batched_tiles(const BatchDesc& d) {
-  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 8) return 1;
+  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 6) return 1;
   const uint32_t tlog = d.alpha > kBTileLog ? d.alpha : kBTileLog;
   return (uint32_t)((d.n + (1ull << tlog) - 1) >> tlog);
 }

@@ -51,7 +51,7 @@ struct Phase {
   uint32_t ready;
   uint32_t pad2[63];
 };
-constexpr int kPhases = 24;
+constexpr int kPhases = 48;  // the tail's own phases, then the levels of its large-k merge sort
 
 // Per-call control block at the head of the workspace; zeroed by k_init.
 struct Ctl {
@@ -74,7 +74,7 @@ struct Ctl {
   uint32_t bstar;           // output bucket holding slot k-1 (buckets after it are not scattered)
   uint32_t bigbucket;       // an output bucket overflows one workgroup: take the select path
   uint32_t ngroups;         // output sort groups
-  uint32_t need_merge;      // the large-k merge-sort kernels must run (select fallback taken)
+  uint32_t need_merge;      // the select fallback was taken with k > kSmallCap (merge-sort phases ran)
   uint32_t wmap;  // monotone map used to cut the delegates: 0 top 11 bits, 1 log-distance
   uint32_t wbin;  // delegates with bin >= wbin form W, a superset of those ranked >= t
   uint32_t wsize; // |W|, known from the fused histogram
@@ -210,6 +210,9 @@ __device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
 }
 __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {

@@ -249,10 +249,11 @@ struct Runner {
       ta.out_vals = out_vals;
       ta.out_idx = out_idx;
       ta.out_kth = out_kth;
+      ta.A = ta.big_sort ? at<uint64_t>(ws, p.off_A) : nullptr;
+      ta.B = ta.big_sort ? at<uint64_t>(ws, p.off_B) : nullptr;
+      ta.M = p.M;
       ta.ctl = ctl;
       launch_tail(p, ta, st);
-      // the merge sort runs only if the tail fell back to its select path
-      if (ta.big_sort && !filter_only) big_sort(p, ws, out_vals, out_idx, out_kth, 1, ctl, st);
       return;
     }
     if (p.mode == 1 && p.variant >= 2) {

@@ -45,6 +45,8 @@ struct TailArgs {
   uint32_t *Q, *ckey, *cidx, *skey, *sidx, *okey, *oidx;
   uint32_t cap_s;
   uint32_t *out_vals, *out_idx, *out_kth;
+  uint64_t *A, *B;  // big_sort: the merge sort's two buffers of M composites
+  uint64_t M;       // k rounded up to a power-of-two multiple of kSortTile
   Ctl* ctl;
 };
 
@@ -634,6 +636,87 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
   }
 }
 
+// ---- large-k sort of the fallback path ---------------------------------------
+// The k compacted entries (okey / oidx) sorted without leaving the kernel:
+// tiles of kSortTile sorted in LDS into A, then runs merged pairwise, one
+// phase per level; an entry's slot in its merged run is its slot in its own
+// run plus the entries of the partner run placed before it (strictly greater
+// for the left run, greater or equal for the right one, so equal pads stay
+// in order).  The last level writes the outputs.
+constexpr int PH_MS = 24;           // phase of the tile sorts; the merge levels follow
+constexpr uint32_t kMChunk = 4096;  // entries per merge claim
+static_assert(PH_MS + 1 + 20 <= kPhases, "merge levels for k < 2^32");
+
+template <int DT>
+__device__ inline void tail_merge_sort(const TailArgs& a, Ctl* ctl, TailSmem& sm) {
+  Phase* ph = ctl->ph;
+  uint64_t* A = a.A;
+  uint64_t* B = a.B;
+  const uint64_t M = a.M;
+  const uint32_t k = a.k;
+  {
+    const uint32_t ntiles = (uint32_t)(M / kSortTile);
+    uint32_t mine = 0;
+    uint64_t* buf = sm.u.sortbuf;
+    for (;;) {
+      const uint32_t c = claim(&ph[PH_MS], ntiles, sm);
+      if (c >= ntiles) break;
+      ++mine;
+      for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile; j += kTailThreads) {
+        const uint64_t i = (uint64_t)c * kSortTile + j;
+        buf[j] = i < k ? comp(ld_coh(&a.okey[i]), ld_coh(&a.oidx[i])) : 0ull;
+      }
+      __syncthreads();
+      lds_sort_desc(buf, kSortTile);
+      for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile; j += kTailThreads)
+        st_coh64(&A[(uint64_t)c * kSortTile + j], buf[j]);
+      __syncthreads();
+    }
+    if (report(&ph[PH_MS], mine, ntiles, sm)) raise_ready(&ph[PH_MS]);
+    wait_ready(&ph[PH_MS], ctl);
+  }
+  int level = 0;
+  for (uint64_t run = kSortTile; run < M; run <<= 1, ++level) {
+    const bool last = 2 * run == M;
+    Phase* P = &ph[PH_MS + 1 + level];
+    const uint32_t nch = (uint32_t)(M / kMChunk);
+    uint32_t mine = 0;
+    for (;;) {
+      const uint32_t c = claim(P, nch, sm);
+      if (c >= nch) break;
+      ++mine;
+      for (uint32_t j = threadIdx.x; j < kMChunk; j += kTailThreads) {
+        const uint64_t i = (uint64_t)c * kMChunk + j;
+        const uint64_t base = i / (2 * run) * (2 * run);
+        const bool left = i - base < run;
+        const uint64_t own = left ? i - base : i - base - run;
+        const uint64_t* other = A + (left ? base + run : base);
+        const uint64_t x = ld_coh64(&A[i]);
+        uint64_t lo = 0, hi = run;
+        while (lo < hi) {
+          const uint64_t mid = (lo + hi) >> 1;
+          const uint64_t y = ld_coh64(&other[mid]);
+          if (left ? y > x : y >= x) lo = mid + 1;
+          else hi = mid;
+        }
+        const uint64_t slot = own + lo;
+        if (last) {
+          if (slot < k) write_out<DT>(x, (uint32_t)slot, k, a.out_vals, a.out_idx, a.out_kth);
+        } else {
+          st_coh64(&B[base + slot], x);
+        }
+      }
+    }
+    if (last) break;
+    if (report(P, mine, nch, sm)) raise_ready(P);
+    wait_ready(P, ctl);
+    uint64_t* t = A;
+    A = B;
+    B = t;
+  }
+  if (blockIdx.x == 0) stamp(ctl, PH_FS);
+}
+
 template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   __shared__ TailSmem sm;
@@ -1073,7 +1156,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
 
   // Fallback for an overfull bucket (massive ties): exact radix select of the
   // k-th survivor, exact compaction, then an LDS sort (k <= kSmallCap) or the
-  // separate merge-sort kernels.
+  // merge sort above, all in this kernel.
   if (threadIdx.x == 0 && blockIdx.x == 0) ctl->need_merge = a.big_sort ? 1u : 0u;
   const uint64_t Tk = tail_select(a.ckey, a.cidx, nc, a.k, ctl->histC, &ph[PH_FSEL], ctl->selpub + 4, ctl, sm);
   if (a.kth_only) {
@@ -1101,8 +1184,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       stamp(ctl, PH_FC);
       raise_ready(&ph[PH_FC]);
     }
-    if (a.big_sort) return;  // k > kSmallCap: the merge-sort kernels follow
     wait_ready(&ph[PH_FC], ctl);
+    if (a.big_sort) {  // k > kSmallCap
+      tail_merge_sort<DT>(a, ctl, sm);
+      return;
+    }
   }
   if (claim(&ph[PH_FS], 1, sm) != 0) return;
   sort_and_write<DT>(a.okey, a.oidx, a.k, 0, a.k, a.k, a.out_vals, a.out_idx, a.out_kth, sm.u.sortbuf,

@@ -20,7 +20,7 @@ keys of n = 2^lg_n (the sum of both times; three interleaved rounds, the
 fastest run counts); an entry is written only where a candidate beats the
 planner by more than 3%.
 
-    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single]
+    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single | --keep-single]
 """
 from __future__ import annotations
 
@@ -169,7 +169,13 @@ def main(argv=None):
     ap.add_argument("--problems", type=int, default=512)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--single", action="store_true", help="also tune single problems (alpha, beta)")
+    ap.add_argument("--keep-single", action="store_true",
+                    help="re-tune the batched form only, keeping the single-problem entries of --out")
     args = ap.parse_args(argv)
+    kept = []
+    if args.keep_single and os.path.exists(args.out):
+        with open(args.out) as f:
+            kept = [e for e in json.load(f)["entries"] if e["form"] == 0]
     import torch
     import paper_2109_08219_amd as drt
     if not torch.cuda.is_available():
@@ -178,6 +184,8 @@ def main(argv=None):
     entries = tune_batched(drt, torch, args.problems, args.reps, log=lambda s: print(s, flush=True))
     if args.single:
         entries += tune_single(drt, torch, max(3, args.reps // 2), log=lambda s: print(s, flush=True))
+    else:
+        entries += kept
     doc = {"device": torch.cuda.get_device_name(0), "problems_per_bucket": args.problems, "reps": args.reps,
            "seconds": round(time.time() - t0, 1), "entries": entries}
     with open(args.out, "w") as f:
