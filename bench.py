@@ -27,6 +27,7 @@ its timed region:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-adversarial] [--no-batched] [--no-serving] [--no-smallest] [--no-by-k] [--no-host]
+                       [--no-wide]
                        [--copy-calibration]
        python bench.py --delegate-vector A:B[,A:B...]
                        (profiling aid: only the delegate vector of the 2^30 uniform input for
@@ -117,7 +118,17 @@ def bench_batched(drt, synth, torch, args):
         drt.topk_select(t, k, v, ix)
     torch.cuda.synchronize()
     ms_loop = (time.perf_counter() - t0) * 1e3
+    # the method's re-read (beta = 1): the k - 1 subranges whose delegate ranks above t, per
+    # problem on the delegate route (route 2); not counted as useful bytes
+    reread = 0
+    routes = {1: 0, 2: 0, 3: 0}
+    for t, k in probs:
+        r, a = drt.batched_route(t.numel(), k)
+        routes[r] = routes.get(r, 0) + 1
+        if r == 2:
+            reread += 4 * min(t.numel(), (k - 1) << a)
     return {"instances": len(probs), "keys": total, "ms_per_batch": ms, "queries_per_s": len(probs) / ms * 1e3,
+            "reread_bytes": reread, "routes": {str(r): c for r, c in routes.items()},
             "GBps": 4.0 * total / ms / 1e6, "loop_ms": ms_loop, "loop_queries_per_s": len(probs) / ms_loop * 1e3,
             "speedup_vs_loop": ms_loop / ms, "steps": steps}
 
@@ -228,6 +239,34 @@ def bench_delegates_vs_plain(drt, torch, t_u):
     return out
 
 
+def bench_wide(drt, torch):
+    """64-bit keys at N = 2^28 (2 GiB, the same bytes as 2^29 4-byte keys): uint64
+    uniform and float64 N(0,1), k in {1, 1024, 131072}; keys/s and GB/s of the
+    mandatory 8-byte read.  Inputs drawn on the GPU."""
+    print("[bench] 64-bit keys: 2^28", file=sys.stderr, flush=True)
+    n = 1 << 28
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20210919)
+    out = []
+    for name in ("u64", "f64"):
+        if name == "u64":
+            t = torch.randint(-2 ** 63, 2 ** 63 - 1, (n,), dtype=torch.int64, device="cuda",
+                              generator=gen).view(torch.uint64)
+        else:
+            t = torch.randn(n, dtype=torch.float64, device="cuda", generator=gen)
+        for k in KS:
+            v = torch.empty(k, dtype=t.dtype, device="cuda")
+            ix = torch.empty(k, dtype=torch.int32, device="cuda")
+            r = _median_ms(torch, lambda: drt.topk_select(t, k, v, ix), 10, 2)
+            p = drt.plan(n, k, name)
+            r.update(dtype=name, k=k, mode=p.mode, alpha=p.alpha, keys_per_s=n / (r["ms_median"] / 1e3),
+                     GBps=8 * n / (r["ms_median"] / 1e3) / 1e9)
+            out.append(r)
+        del t
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_inner_by_k(drt, torch, t_u):
     """The top-k algorithm the delegates assist, by k (the paper's choice of
     algorithm as k grows, Sections 5.1 and 6.1): N = 2^28 uint32 uniform, the
@@ -328,6 +367,7 @@ def main() -> int:
     ap.add_argument("--no-adversarial", action="store_true")
     ap.add_argument("--no-smallest", action="store_true", help="skip the k smallest / int32 cases")
     ap.add_argument("--no-host", action="store_true", help="skip top-k of keys in host memory")
+    ap.add_argument("--no-wide", action="store_true", help="skip the 64-bit key cases")
     ap.add_argument("--no-by-k", action="store_true",
                     help="skip the by-k studies (delegates against the plain radix select, the inner "
                          "top-k algorithm) and the 2^27 shard cases")
@@ -491,6 +531,7 @@ def main() -> int:
     del t_u, t_f
     torch.cuda.empty_cache()
     small = bench_small(drt, synth, torch, args)
+    wide = None if args.no_wide else bench_wide(drt, torch)
     adversarial = None if args.no_adversarial else bench_adversarial(drt, torch, args)
     batched = None if args.no_batched else bench_batched(drt, synth, torch, args)
     serving = None if args.no_serving else bench_serving(drt, synth, torch, np)
@@ -524,6 +565,7 @@ def main() -> int:
         "smallest_and_i32": smallest_i32,
         "delegates_vs_plain_radix": by_k,
         "inner_by_k": inner_by_k,
+        "wide_keys": wide,
         "shard_2p27": shard,
         "host_stream": host_stream,
         "adversarial": adversarial,

@@ -26,7 +26,7 @@ constexpr int kBT = 512;                  // threads per workgroup (two workgrou
 constexpr int kBWaves = kBT / 64;
 constexpr uint32_t kBSmallN = 4096;       // problems this small are selected in LDS directly
 constexpr uint32_t kBMaxS = 4096;         // delegate vector capacity (LDS)
-constexpr uint32_t kBMaxSG = 16384;       // delegate vector of a split problem (global memory)
+constexpr uint32_t kBMaxSG = 32768;       // delegate vector of a split problem (global memory)
 constexpr uint32_t kBSurv = 4096;         // survivor capacity (LDS)
 constexpr uint32_t kBMaxK = 2048;         // largest k handled in a workgroup
 constexpr uint64_t kBMaxN = 1ull << 22;   // largest n handled in a workgroup
@@ -34,7 +34,11 @@ constexpr int kBU = 8;                    // 1 KiB wave loads in flight per wave
 constexpr uint32_t kBStep = 256 * kBU;    // keys per wave step
 constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 for gfx9-family raw buffers
 constexpr uint32_t kBTileLog = 18;        // a split problem's delegate vector is built in tiles of
-                                          // 2^max(kBTileLog, alpha) keys, one workgroup each
+                                          // 2^max(kBTileLog, alpha) keys, one workgroup each (2^(alpha + 12)
+                                          // below alpha 6, so a tile's 4096 delegates fit its LDS)
+__host__ __device__ constexpr uint32_t tile_log(uint32_t alpha) {
+  return alpha + 12 < kBTileLog ? alpha + 12 : (alpha > kBTileLog ? alpha : kBTileLog);
+}
 
 // One problem as the kernel sees it (64 bytes).
 struct BatchDesc {
@@ -56,6 +60,8 @@ struct BatchSmem {
   uint64_t surv[kBSurv];  // survivors, also the exchange buffer of their sort
   uint32_t hist[kBins];   // digit histograms; then the list of qualifying subranges
   uint32_t wsum[kBWaves];
+  uint32_t wbig[kBWaves];
+  uint64_t red[2 * kBWaves];
   uint64_t sel;
   uint64_t tail_del;      // delegate of the subrange holding the last n mod 4 keys
   uint32_t nsurv;
@@ -181,6 +187,19 @@ __device__ __forceinline__ void b_write_out(uint64_t c, uint32_t r, uint32_t k, 
   if (out_kth && r == k - 1) *out_kth = v;
 }
 
+// Wave-wide append to an LDS list: the lanes with `pred` take consecutive
+// slots from *count with one LDS atomic per wave (whole wave active); slots at
+// or past cap are counted but not stored.
+__device__ __forceinline__ void lds_append(bool pred, uint64_t x, uint32_t* count, uint64_t* list, uint32_t cap) {
+  const uint64_t b = __ballot(pred);
+  if (!b) return;
+  const int leader = __ffsll((unsigned long long)b) - 1;
+  uint32_t base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(b));
+  base = (uint32_t)__shfl((int)base, leader) + mbcnt(b);
+  if (pred && base < cap) list[base] = x;
+}
+
 // Sorts `cnt` composites from LDS array `src` and writes the first `k` as
 // outputs 0..k-1.  `src` holds at least E * kBT entries and serves as the
 // exchange buffer of the sort once every thread has loaded its elements.
@@ -201,9 +220,120 @@ __device__ __noinline__ void b_sort_write_e(uint64_t* src, uint32_t cnt, uint32_
   }
 }
 
-// cnt <= kBT * 8, k <= cnt.
+// Bucket-rank sort of the cnt (<= E * kBT) distinct composites src[0..cnt),
+// writing the first k as outputs: the composites are binned by the top 11
+// bits of their distance from the smallest (bin 0 holds the largest),
+// counted in `bins` (kBins words), scattered bin by bin into `buf`, and each
+// takes the slot (start of its bin) + (number of larger composites in its
+// bin).  Gives up (false, nothing written) when a bin holds more than
+// kRankMaxBin: keys crowded into a narrow range go to the network instead.
+template <int E>
+__device__ __noinline__ bool b_rank_write_e(const uint64_t* src, uint32_t cnt, uint32_t k, uint32_t* out_vals,
+                                            uint32_t* out_idx, uint32_t* out_kth, Codec cx, uint64_t* buf,
+                                            uint32_t* bins, BatchSmem& sm) {
+  constexpr int NW = kBWaves, PER = kBins / kBT;
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+  uint64_t v[E];
+  uint64_t mx = 0, nmn = 0;  // largest composite, and the complement of the smallest
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = e * kBT + t;
+    v[e] = g < cnt ? src[g] : 0ull;
+    if (g < cnt) {
+      mx = v[e] > mx ? v[e] : mx;
+      nmn = ~v[e] > nmn ? ~v[e] : nmn;
+    }
+  }
+  mx = wave_max64(mx);
+  nmn = wave_max64(nmn);
+  __syncthreads();  // src may alias the reduction slots' neighbours: every load done
+  if (lane == 0) {
+    sm.red[w] = mx;
+    sm.red[NW + w] = nmn;
+  }
+  for (int i = t; i < kBins; i += kBT) bins[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    mx = sm.red[i] > mx ? sm.red[i] : mx;
+    nmn = sm.red[NW + i] > nmn ? sm.red[NW + i] : nmn;
+  }
+  const uint64_t lo = ~nmn;
+  const uint32_t bits = bitlen64(mx - lo);
+  const uint32_t sh = bits > 11u ? bits - 11u : 0u;
+  uint32_t b[E], r[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t g = e * kBT + t;
+    b[e] = (uint32_t)(kBins - 1) - (uint32_t)((v[e] - lo) >> sh);
+    r[e] = g < cnt ? atomicAdd(&bins[b[e]], 1u) : 0u;
+  }
+  __syncthreads();
+  uint32_t c[PER], sum = 0, big = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    c[j] = bins[t * PER + j];
+    sum += c[j];
+    big = c[j] > big ? c[j] : big;
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, d);
+    if (lane >= d) inc += y;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t y = (uint32_t)__shfl_xor((int)big, o);
+    big = y > big ? y : big;
+  }
+  if (lane == 63) sm.wsum[w] = inc;
+  if (lane == 0) sm.wbig[w] = big;
+  __syncthreads();
+  uint32_t off = inc - sum;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if ((uint32_t)i < w) off += sm.wsum[i];
+    big = sm.wbig[i] > big ? sm.wbig[i] : big;
+  }
+  if (big > kRankMaxBin) {  // block-uniform
+    __syncthreads();
+    return false;
+  }
+  __syncthreads();  // every count read before it becomes a bin start
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    bins[t * PER + j] = off;
+    off += c[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (e * kBT + t < cnt) buf[bins[b[e]] + r[e]] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e * kBT + t >= cnt) continue;
+    const uint32_t st = bins[b[e]], en = b[e] + 1 < (uint32_t)kBins ? bins[b[e] + 1] : cnt;
+    uint32_t slot = st;
+    for (uint32_t j = st; j < en; ++j) slot += buf[j] > v[e] ? 1u : 0u;
+    if (slot < k) b_write_out(v[e], slot, k, out_vals, out_idx, out_kth, cx);
+  }
+  __syncthreads();  // the caller reuses the LDS
+  return true;
+}
+
+// cnt <= kBT * 8, k <= cnt.  `buf` (cnt entries) and `bins` (kBins words) are
+// free LDS that the bucket-rank sort may use; src must not alias them.
 __device__ inline void b_sort_write(uint64_t* src, uint32_t cnt, uint32_t k, uint32_t* out_vals, uint32_t* out_idx,
-                                    uint32_t* out_kth, Codec cx) {
+                                    uint32_t* out_kth, Codec cx, uint64_t* buf, uint32_t* bins, BatchSmem& sm) {
+  if (cnt > 1u * kBT) {
+    bool done;
+    if (cnt <= 2u * kBT) done = b_rank_write_e<2>(src, cnt, k, out_vals, out_idx, out_kth, cx, buf, bins, sm);
+    else if (cnt <= 4u * kBT) done = b_rank_write_e<4>(src, cnt, k, out_vals, out_idx, out_kth, cx, buf, bins, sm);
+    else done = b_rank_write_e<8>(src, cnt, k, out_vals, out_idx, out_kth, cx, buf, bins, sm);
+    if (done) return;
+  }
   if (cnt <= 1u * kBT) b_sort_write_e<1>(src, cnt, k, out_vals, out_idx, out_kth, cx);
   else if (cnt <= 2u * kBT) b_sort_write_e<2>(src, cnt, k, out_vals, out_idx, out_kth, cx);
   else if (cnt <= 4u * kBT) b_sort_write_e<4>(src, cnt, k, out_vals, out_idx, out_kth, cx);
@@ -273,7 +403,8 @@ __device__ inline void b_small(const BatchDesc& d, BatchSmem& sm) {
     cnt = k;
     src = sm.D;
   }
-  b_sort_write(src, cnt, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
+  b_sort_write(src, cnt, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype), src == sm.D ? sm.surv : sm.D,
+               sm.hist, sm);
 }
 
 // Block-level MSD radix select over the problem's 64-bit composites: each
@@ -334,10 +465,7 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm, uint32_t* rec)
       for (int c = 0; c < 4; ++c) {
         const uint32_t i = base + j * 256 + lane * 4 + c;
         const uint64_t x = comp(cx.enc(v[j][c]), i);
-        if (i < n4 && (x & mask) >= prefix) {
-          const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
-          if (slot < kBSurv) sm.surv[slot] = x;
-        }
+        lds_append(i < n4 && (x & mask) >= prefix, x, &sm.nsurv, sm.surv, kBSurv);
       }
   }
   if (threadIdx.x == 0)
@@ -352,7 +480,7 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm, uint32_t* rec)
   const uint32_t ns = sm.nsurv < kBSurv ? sm.nsurv : kBSurv;
   // the class chosen last fits by construction (a single member after the last digit)
   if (threadIdx.x == 0 && sm.nsurv > kBSurv) record_err(rec, ERR_CAP);
-  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
+  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype), sm.D, sm.hist, sm);
 }
 
 // Delegate vector for subranges of at least 256 keys, over the keys
@@ -472,10 +600,7 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
       for (int c = 0; c < 4; ++c) {
         const uint32_t p = pb[j] + c;
         const uint64_t x = comp(cx.enc(v[j][c]), p);
-        if (p < n4 && x >= t) {
-          const uint32_t slot = atomicAdd(&sm.nsurv, 1u);
-          if (slot < kBSurv) sm.surv[slot] = x;
-        }
+        lds_append(p < n4 && x >= t, x, &sm.nsurv, sm.surv, kBSurv);
       }
   }
 }
@@ -513,7 +638,7 @@ __device__ inline bool b_finish(const BatchDesc& d, uint32_t cnt, BatchSmem& sm)
   __syncthreads();
   const uint32_t ns = sm.nsurv;
   if (ns > kBSurv) return false;
-  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype));
+  b_sort_write(sm.surv, ns, k, d.out_vals, d.out_idx, d.out_kth, codec_of(d.dtype), sm.D, sm.hist, sm);
   return true;
 }
 
@@ -606,7 +731,7 @@ template <bool VEC>
 __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
                               uint32_t* rec) {
   const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
-  const uint32_t tlog = alpha > kBTileLog ? alpha : kBTileLog;
+  const uint32_t tlog = tile_log(alpha);
   const uint32_t lo = tile << tlog;
   const uint32_t hi = n - lo > (1u << tlog) ? lo + (1u << tlog) : n;
   const uint32_t s0 = lo >> alpha;

@@ -479,13 +479,13 @@ int batched_alpha(uint64_t n, uint32_t k) {
   if (n > (1ull << kBTileLog)) {
     // split across workgroups: the delegate vector lives in global memory, so
     // it may hold up to kBMaxSG entries and Rule 4's shorter subranges apply
-    // (at least 64 keys: a tile's delegates still fit its workgroup's LDS);
-    // fewer subranges re-read at the same k
+    // (at least 16 keys; tiles shrink so a tile's delegates fit its
+    // workgroup's LDS); fewer subranges re-read at the same k
     if (a < 0) a = rule_alpha(n, k);
-    if (a < 6) a = 6;
+    if (a < 4) a = 4;
     if (a > 24) a = 24;
     while (a < 24 && subranges(a) > kBMaxSG) ++a;
-    while (subranges(a) < 2ull * k && a > 6) --a;
+    while (subranges(a) < 2ull * k && a > 4 && subranges(a - 1) <= kBMaxSG) --a;
     return subranges(a) > k ? a : 0;
   }
   if (a < 0) {
@@ -522,10 +522,10 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
 
 // Tiles of a problem's delegate vector (one workgroup each): problems of
 // more than 2^kBTileLog keys on the delegate route are split so several
-// workgroups stream them (their subranges hold at least 64 keys).
+// workgroups stream them (their subranges hold at least 16 keys).
 uint32_t batched_tiles(const BatchDesc& d) {
-  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 6) return 1;
-  const uint32_t tlog = d.alpha > kBTileLog ? d.alpha : kBTileLog;
+  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 4) return 1;
+  const uint32_t tlog = tile_log(d.alpha);
   return (uint32_t)((d.n + (1ull << tlog) - 1) >> tlog);
 }
 
@@ -840,12 +840,21 @@ int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes) {
     *bytes = 8 * n + 12ull * k + 8 + wp.total;
     return DRTOPK_OK;
   }
-  uint64_t ws = sizeof(BatchDesc);
+  // a batched problem: its descriptor, work items and arrival counter, plus
+  // the global delegate vector when it is split across workgroups
+  uint64_t ws = sizeof(BatchDesc) + 16;
   if (!batched_eligible(n, k)) {
     Plan p;
     st = make_plan(dummy, n, k, dtype, nullptr, &p);
     if (st) return st;
     ws = p.total;
+  } else {
+    BatchDesc d{};
+    d.n = n;
+    d.k = k;
+    d.alpha = (uint32_t)batched_alpha(n, k);
+    d.tiles = batched_tiles(d);
+    if (d.tiles > 1) ws += 4ull * d.tiles + 8ull * ((n + (1ull << d.alpha) - 1) >> d.alpha);
   }
   *bytes = 4 * n + 8ull * k + 4 + ws;
   return DRTOPK_OK;

@@ -324,19 +324,61 @@ __global__ __launch_bounds__(kWThreads) void k_wfind(const uint64_t* __restrict_
   }
 }
 
-// Wave-wide append with one atomic per wave (whole wave active); entries at
-// or past cap are dropped and flagged.
-__device__ __forceinline__ void wappend(bool pred, uint32_t* counter, uint32_t cap, uint64_t* gkey, uint32_t* gidx,
-                                        uint64_t k, uint32_t p, WCtl* ctl) {
-  const uint32_t slot = wave_append(pred, counter);
+// Appends staged in LDS: the lanes of a wave take consecutive stage slots
+// with one LDS atomic, and the block reserves global space with one device
+// atomic per flush (a single global counter taking an atomic per wave is
+// what the device serialises).  Entries at or past cap are dropped and
+// flagged.
+constexpr uint32_t kWStage = 2048;
+struct WStage {
+  uint64_t key[kWStage];
+  uint32_t idx[kWStage];
+  uint32_t n;
+  uint32_t base;
+};
+
+__device__ __forceinline__ void wstage_init(WStage& S) {
+  if (threadIdx.x == 0) S.n = 0;
+  __syncthreads();
+}
+
+// Whole wave active.
+__device__ __forceinline__ void wstage_push(WStage& S, bool pred, uint64_t k, uint32_t p) {
+  const uint64_t b = __ballot(pred);
+  if (!b) return;
+  const int leader = __ffsll((unsigned long long)b) - 1;
+  uint32_t off = 0;
+  if ((int)lane_id() == leader) off = atomicAdd(&S.n, (uint32_t)__popcll(b));
+  off = (uint32_t)__shfl((int)off, leader) + mbcnt(b);
   if (pred) {
-    if (slot < cap) {
-      gkey[slot] = k;
-      if (gidx) gidx[slot] = p;
+    S.key[off] = k;
+    S.idx[off] = p;
+  }
+}
+
+// Block-uniform: flushes when `force` or when fewer than kWThreads slots are
+// left (one more step of the block could fill them).  gidx may be null.
+__device__ inline void wstage_flush(WStage& S, uint32_t* counter, uint32_t cap, uint64_t* gkey, uint32_t* gidx,
+                                    WCtl* ctl, bool force) {
+  __syncthreads();
+  const uint32_t n = S.n;
+  const bool doit = n != 0 && (force || n + kWThreads > kWStage);
+  __syncthreads();
+  if (!doit) return;
+  if (threadIdx.x == 0) S.base = atomicAdd(counter, n);
+  __syncthreads();
+  const uint32_t base = S.base;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (base + i < cap) {
+      gkey[base + i] = S.key[i];
+      if (gidx) gidx[base + i] = S.idx[i];
     } else {
       wflag(ctl, ERR_CAP);
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) S.n = 0;
+  __syncthreads();
 }
 
 // Subranges whose delegate ranks at or above t: the only ones that can hold
@@ -344,16 +386,42 @@ __device__ __forceinline__ void wappend(bool pred, uint32_t* counter, uint32_t c
 __global__ __launch_bounds__(kWThreads) void k_wqualify(const uint64_t* __restrict__ dkey,
                                                         const uint32_t* __restrict__ didx, uint64_t S, WCtl* ctl,
                                                         uint32_t* Q) {
+  __shared__ uint32_t sq[kWStage];
+  __shared__ uint32_t sn, sbase;
+  if (threadIdx.x == 0) sn = 0;
+  __syncthreads();
   const u128 t = ctl->sel[0].t;
+  const uint32_t cap = ctl->cap_q;
   const uint64_t stride = (uint64_t)gridDim.x * kWThreads;
-  for (uint64_t b = (uint64_t)blockIdx.x * kWThreads; b < S; b += stride) {
-    const uint64_t s = b + threadIdx.x;
-    const bool q = s < S && wcomp(dkey[s], didx[s]) >= t;
-    const uint32_t slot = wave_append(q, &ctl->nq);
-    if (q) {
-      if (slot < ctl->cap_q) Q[slot] = (uint32_t)s;
-      else wflag(ctl, ERR_CAP);
+  for (uint64_t b = (uint64_t)blockIdx.x * kWThreads;; b += stride) {
+    const bool more = b < S;
+    if (more) {
+      const uint64_t s = b + threadIdx.x;
+      const bool q = s < S && wcomp(dkey[s], didx[s]) >= t;
+      const uint64_t m = __ballot(q);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t off = 0;
+        if ((int)lane_id() == leader) off = atomicAdd(&sn, (uint32_t)__popcll(m));
+        off = (uint32_t)__shfl((int)off, leader) + mbcnt(m);
+        if (q) sq[off] = (uint32_t)s;
+      }
     }
+    __syncthreads();
+    const uint32_t n = sn;
+    if (n != 0 && (!more || n + kWThreads > kWStage)) {
+      __syncthreads();
+      if (threadIdx.x == 0) sbase = atomicAdd(&ctl->nq, n);
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (sbase + i < cap) Q[sbase + i] = sq[i];
+        else wflag(ctl, ERR_CAP);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) sn = 0;
+    }
+    __syncthreads();
+    if (!more) break;
   }
 }
 
@@ -363,6 +431,8 @@ __global__ __launch_bounds__(kWThreads) void k_wqualify(const uint64_t* __restri
 __global__ __launch_bounds__(kWThreads) void k_wscan(const uint64_t* __restrict__ keys, uint64_t n, int alpha,
                                                      Codec64 cd, const uint32_t* __restrict__ Q, WCtl* ctl,
                                                      uint64_t* ckey, uint32_t* cidx) {
+  __shared__ WStage st;
+  wstage_init(st);
   const u128 t = ctl->sel[0].t;
   const uint32_t nq = ctl->nq < ctl->cap_q ? ctl->nq : ctl->cap_q;
   const uint64_t total = (uint64_t)nq << alpha, mask = (1ull << alpha) - 1;
@@ -381,8 +451,10 @@ __global__ __launch_bounds__(kWThreads) void k_wscan(const uint64_t* __restrict_
         keep = wcomp(k, p) >= t;
       }
     }
-    wappend(keep, &ctl->nc, cap, ckey, cidx, k, p, ctl);
+    wstage_push(st, keep, k, p);
+    wstage_flush(st, &ctl->nc, cap, ckey, cidx, ctl, false);
   }
+  wstage_flush(st, &ctl->nc, cap, ckey, cidx, ctl, true);
 }
 
 // LDS bitonic sort, descending, of P (power of two) composites.
@@ -444,6 +516,8 @@ __global__ __launch_bounds__(kWThreads) void k_wcompact(const uint64_t* __restri
                                                         const uint32_t* count, uint32_t cap, Codec64 cd, int which,
                                                         uint32_t k, WCtl* ctl, uint64_t* okey, uint32_t* oidx) {
   if (ctl->finished) return;
+  __shared__ WStage st;
+  wstage_init(st);
   const u128 T = ctl->sel[which].t;
   if (count) {
     const uint32_t c = *count;
@@ -458,8 +532,10 @@ __global__ __launch_bounds__(kWThreads) void k_wcompact(const uint64_t* __restri
       c = wentry<SRC>(key, pos, i, cd);
       keep = c >= T;
     }
-    wappend(keep, &ctl->no, k, okey, oidx, wkey(c), wpos(c), ctl);
+    wstage_push(st, keep, wkey(c), wpos(c));
+    wstage_flush(st, &ctl->no, k, okey, oidx, ctl, false);
   }
+  wstage_flush(st, &ctl->no, k, okey, oidx, ctl, true);
 }
 
 // Sort of the k compacted outputs, k <= kWSmall: one workgroup.

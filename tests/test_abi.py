@@ -204,15 +204,15 @@ def test_batched_routes_without_gpu():
                     continue
                 S = -(-n // (1 << a))
                 # one workgroup's LDS holds the delegate vector; problems split across
-                # workgroups (n > 2^18) keep it in global memory, up to 16384 entries,
-                # with subranges of at least 64 keys
+                # workgroups (n > 2^18) keep it in global memory, up to 32768 entries,
+                # with subranges of at least 16 keys
                 if n > (1 << 18):
-                    assert r == 2 and 6 <= a <= 24 and k < S <= 16384, (n, k, r, a)
+                    assert r == 2 and 4 <= a <= 24 and k < S <= 32768, (n, k, r, a)
                 else:
                     assert r == 2 and 2 <= a <= 24 and k < S <= 4096, (n, k, r, a)
         assert drt.batched_route(1 << 20, 1) == (2, 11)  # Rule 4: floor((20 - 0 + 3) / 2)
         assert drt.batched_route(1 << 20, 1024) == (2, 6)  # Rule 4: floor((20 - 10 + 3) / 2)
-        assert drt.batched_route(1 << 22, 2048) == (2, 8)  # Rule 4 gives 7: raised until S <= 16384
+        assert drt.batched_route(1 << 22, 2048) == (2, 7)  # Rule 4: floor((22 - 11 + 3) / 2), S = 32768
         assert drt.batched_route((1 << 22) + 1, 1) == (0, 0)
         assert drt.batched_route(1 << 20, 2049) == (0, 0)
         drt.tune_set([(drt.FORM_BATCHED, 16, 2, 3, 1)])
@@ -243,7 +243,11 @@ def test_server_and_footprint_arguments_without_gpu():
     assert L.drtopk_server_drain(None) == 1
     assert L.drtopk_server_destroy(None) == 1
     # footprint: input + outputs + workspace of the route
-    assert drt.footprint(1000, 10) == 4000 + 84 + 64
+    # (a batched problem: its 64-byte descriptor plus work item and arrival counter)
+    assert drt.footprint(1000, 10) == 4000 + 84 + 64 + 16
+    # a batched problem split across workgroups also holds its global delegate vector
+    r, a = drt.batched_route(1 << 20, 1000)
+    assert drt.footprint(1 << 20, 1000) == 4 * (1 << 20) + 8004 + 80 + 4 * 4 + 8 * ((1 << 20) >> a)
     assert drt.footprint(1 << 24, 100) > 4 * (1 << 24) + 804
     b = ctypes.c_uint64()
     assert L.drtopk_footprint(10, 11, 0, ctypes.byref(b)) == 1
