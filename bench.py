@@ -118,17 +118,21 @@ def bench_batched(drt, synth, torch, args):
         drt.topk_select(t, k, v, ix)
     torch.cuda.synchronize()
     ms_loop = (time.perf_counter() - t0) * 1e3
-    # the method's re-read (beta = 1): the k - 1 subranges whose delegate ranks above t, per
-    # problem on the delegate route (route 2); not counted as useful bytes
+    # the method's re-read per problem on the delegate route (route 2), not counted as useful
+    # bytes: beta 1 re-reads exactly the k - 1 subranges whose delegate ranks above t; beta 2
+    # at most (k - 1) / 2 subranges (those whose second delegate does), counted at that bound
     reread = 0
     routes = {1: 0, 2: 0, 3: 0}
+    betas = {1: 0, 2: 0}
     for t, k in probs:
-        r, a = drt.batched_route(t.numel(), k)
+        r, a, beta = drt.batched_plan(t.numel(), k)
         routes[r] = routes.get(r, 0) + 1
         if r == 2:
-            reread += 4 * min(t.numel(), (k - 1) << a)
+            betas[beta] = betas.get(beta, 0) + 1
+            reread += 4 * min(t.numel(), ((k - 1) // beta) << a)
     return {"instances": len(probs), "keys": total, "ms_per_batch": ms, "queries_per_s": len(probs) / ms * 1e3,
             "reread_bytes": reread, "routes": {str(r): c for r, c in routes.items()},
+            "route2_beta": {str(b): c for b, c in betas.items()},
             "GBps": 4.0 * total / ms / 1e6, "loop_ms": ms_loop, "loop_queries_per_s": len(probs) / ms_loop * 1e3,
             "speedup_vs_loop": ms_loop / ms, "steps": steps}
 

@@ -141,9 +141,11 @@ int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* 
  * floor(log2 n) and floor(log2 k) equal lg_n and lg_k:
  *   form 0 (DRTOPK_FORM_SINGLE): topk_select / kth_select planning, alpha and
  *          beta as in drtopk_options_t (explicit options still win);
- *   form 1 (DRTOPK_FORM_BATCHED): the subrange exponent of a batched problem
- *          owned by one workgroup (beta is 1 there; the kernel raises alpha
- *          until the delegate vector fits its LDS).
+ *   form 1 (DRTOPK_FORM_BATCHED): the subrange exponent and delegates per
+ *          subrange (beta 2; any other value means 1) of a batched problem
+ *          (the planner raises alpha until the delegate vector, S * beta
+ *          entries, fits the workgroup's LDS or, for a problem split across
+ *          workgroups, its global buffer).
  * Problems with no entry use Rule 4 (const 3).  drtopk_tune_set replaces the
  * whole table (count 0 clears it); entries are validated (alpha 0..24, beta
  * 1/2/4/8) and copied.  The table is process-wide. */
@@ -162,10 +164,11 @@ int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count);
 /* How a batched problem of this shape is run (no device work):
  *   *route 0 = single-problem path, 1 = sorted outright in the workgroup,
  *          2 = delegate method in the workgroup with subrange exponent
- *          *alpha, 3 = workgroup radix select without delegates.
+ *          *alpha and *beta delegates per subrange (1 or 2; beta may be
+ *          NULL), 3 = workgroup radix select without delegates.
  * Route 2 falls back to route 3 on the device when the survivors of an
  * input exceed the workgroup's capacity (4096). */
-int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha);
+int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha, int32_t* beta);
 
 /* Explicit method parameters (for tests, tuning and ablations).
  *   alpha  subrange = 2^alpha elements (Section 5.1), at most 24; -1 = planner's choice
@@ -199,14 +202,18 @@ typedef struct {
   uint64_t delegates;    /* |D| = S * beta */
   uint64_t scanned;      /* subranges re-read after the threshold */
   uint64_t candidates;   /* survivors handed to the second select */
-  uint32_t t_key_bits;   /* the k-th delegate (Rule 2), input bit pattern */
-  uint32_t t_idx;        /* its position */
+  uint32_t t_key_bits;   /* the filter's threshold (Rule 2): the k-th delegate, or a
+                            composite ranked at or below it; input bit pattern */
+  uint32_t t_idx;        /* its position (a bound, possibly past n, when the
+                            threshold is not an element) */
   /* completion time of each step after the delegate pass, in ns since that
    * part started (device clock; 0 = step not run), default variant:
    * [0] refined threshold, [1] Rule 3 over the delegates, [2] re-read,
    * [3] output sorted by one workgroup, [4] output buckets counted,
    * [5] scattered, [6] bucket groups sorted, [7..12] select passes (tie
-   * fallback), [13] exact compaction, [14] fallback sort */
+ * fallback), [13] exact compaction, [14] fallback sort, [15..19] the first
+ * five digit passes of the delegate select (massive ties at the threshold;
+ * the key digits are skipped when the bin holding t is one key) */
   uint32_t step_ns[20];
   uint32_t err_flags;    /* internal consistency checks that failed (0 = none) */
 } drtopk_stats_t;

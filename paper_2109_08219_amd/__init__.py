@@ -104,7 +104,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(u64)],
             "drtopk_tune_set": [ctypes.POINTER(Tune), u32],
             "drtopk_tune_get": [ctypes.POINTER(Tune), u32, ctypes.POINTER(u32)],
-            "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+            "drtopk_batched_alpha": [u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)],
             "drtopk_footprint": [u64, u32, i32, ctypes.POINTER(u64)],
             "drtopk_read_probe": [vp, u64, vp, vp],
             "topk_select_host": [vp, u64, u32, i32, u64, vp, vp, vp],
@@ -427,12 +428,19 @@ def load_tuning(path: str = TUNING_PATH) -> int:
     return len(entries)
 
 
+def batched_plan(n: int, k: int) -> tuple[int, int, int]:
+    """(route, alpha, beta) of a batched problem: route 0 single-problem path, 1 sorted in the
+    workgroup, 2 delegate method in the workgroup (alpha, beta delegates per subrange),
+    3 workgroup radix select."""
+    r, a, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().drtopk_batched_alpha(n, k, ctypes.byref(r), ctypes.byref(a), ctypes.byref(b)),
+           "drtopk_batched_alpha")
+    return r.value, a.value, b.value
+
+
 def batched_route(n: int, k: int) -> tuple[int, int]:
-    """(route, alpha) of a batched problem: route 0 single-problem path, 1 sorted in the
-    workgroup, 2 delegate method in the workgroup (alpha), 3 workgroup radix select."""
-    r, a = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().drtopk_batched_alpha(n, k, ctypes.byref(r), ctypes.byref(a)), "drtopk_batched_alpha")
-    return r.value, a.value
+    """(route, alpha) of a batched problem (batched_plan without beta)."""
+    return batched_plan(n, k)[:2]
 
 
 def footprint(n: int, k: int, dtype: str = "u32") -> int:

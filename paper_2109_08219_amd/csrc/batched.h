@@ -3,11 +3,13 @@
 // Each workgroup (kBT threads) takes whole problems from an atomic counter,
 // largest first (the host orders them), and runs the delegate method for one
 // problem entirely in its LDS:
-//   delegate vector (Rule 1, beta = 1): one wave per subrange of 2^alpha keys;
+//   delegate vector (Rules 1 and 3): the top beta (1 or 2) of each subrange
+//     of 2^alpha keys, built in LDS by waves streaming the keys;
 //   t = the k-th largest delegate: an LDS radix select over the delegates;
-//   survivors (Rule 2): t itself plus every element ranked >= t in the k-1
-//     subranges whose delegate ranks above t (an element >= t lies either in
-//     such a subrange or is t), read as one virtual concatenated vector;
+//   survivors (Rules 2 and 3): t itself, every element ranked >= t in the
+//     subranges whose last delegate ranks above t (read as one virtual
+//     concatenated vector), and with beta = 2 the first delegates above t of
+//     the other subranges;
 //   output: survivors sorted in registers, the first k written.
 // Problems of at most kBSmallN keys are selected in LDS directly (the k-th
 // by radix select, then the k at or above it sorted).  A problem whose
@@ -34,10 +36,11 @@ constexpr int kBU = 8;                    // 1 KiB wave loads in flight per wave
 constexpr uint32_t kBStep = 256 * kBU;    // keys per wave step
 constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 for gfx9-family raw buffers
 constexpr uint32_t kBTileLog = 18;        // a split problem's delegate vector is built in tiles of
-                                          // 2^max(kBTileLog, alpha) keys, one workgroup each (2^(alpha + 12)
-                                          // below alpha 6, so a tile's 4096 delegates fit its LDS)
-__host__ __device__ constexpr uint32_t tile_log(uint32_t alpha) {
-  return alpha + 12 < kBTileLog ? alpha + 12 : (alpha > kBTileLog ? alpha : kBTileLog);
+                                          // 2^max(kBTileLog, alpha) keys, one workgroup each (fewer where a
+                                          // tile's delegates would not fit its LDS: at most 4096 entries)
+__host__ __device__ constexpr uint32_t tile_log(uint32_t alpha, uint32_t beta) {
+  return alpha + 12 - (beta > 1 ? 1 : 0) < kBTileLog ? alpha + 12 - (beta > 1 ? 1 : 0)
+                                                     : (alpha > kBTileLog ? alpha : kBTileLog);
 }
 
 // One problem as the kernel sees it (64 bytes).
@@ -46,7 +49,8 @@ struct BatchDesc {
   uint64_t n;
   uint32_t k;
   uint32_t dtype;
-  uint32_t alpha;  // subrange exponent, >= 2; 0 = radix select without delegates
+  uint16_t alpha;  // subrange exponent, >= 2; 0 = radix select without delegates
+  uint16_t beta;   // delegates per subrange (Rule 3): 1 or 2
   uint32_t tiles;  // > 1: the delegate vector is built by this many workgroups
   uint32_t* out_vals;
   uint32_t* out_idx;
@@ -88,6 +92,64 @@ __device__ __forceinline__ uint64_t group_max64(uint64_t m, uint32_t G) {
 }
 __device__ __forceinline__ uint64_t wave_max64(uint64_t m) {
   return max_cross<32>(max_cross<16>(max_cross<8>(max_cross<4>(max_cross<2>(max_cross<1>(m))))));
+}
+
+// The top BETA (1 or 2) of a stream of distinct composites, m1 > m2 (0 =
+// none yet; 0 is below every composite of a real element, so pushing it
+// changes nothing).
+template <int BETA>
+__device__ __forceinline__ void top_push(uint64_t& m1, uint64_t& m2, uint64_t x) {
+  if constexpr (BETA == 2) {
+    const uint64_t lo = x < m1 ? x : m1;
+    m2 = lo > m2 ? lo : m2;
+  }
+  m1 = x > m1 ? x : m1;
+}
+template <int BETA>
+__device__ __forceinline__ void top_merge(uint64_t& m1, uint64_t& m2, uint64_t b1, uint64_t b2) {
+  if constexpr (BETA == 2) {
+    const uint64_t lo = b1 < m1 ? b1 : m1;
+    const uint64_t hi2 = b2 > m2 ? b2 : m2;
+    m2 = lo > hi2 ? lo : hi2;
+  }
+  m1 = b1 > m1 ? b1 : m1;
+}
+template <int BETA, int M>
+__device__ __forceinline__ void top_cross(uint64_t& m1, uint64_t& m2) {
+  const uint64_t b1 = lane_cross64<M>(m1);
+  const uint64_t b2 = BETA == 2 ? lane_cross64<M>(m2) : 0ull;
+  top_merge<BETA>(m1, m2, b1, b2);
+}
+// Top BETA over each block of G consecutive lanes (G a wave-uniform power of
+// two, at most 64), held by all of its lanes.
+template <int BETA>
+__device__ __forceinline__ void group_top(uint64_t& m1, uint64_t& m2, uint32_t G) {
+  if (G > 1) top_cross<BETA, 1>(m1, m2);
+  if (G > 2) top_cross<BETA, 2>(m1, m2);
+  if (G > 4) top_cross<BETA, 4>(m1, m2);
+  if (G > 8) top_cross<BETA, 8>(m1, m2);
+  if (G > 16) top_cross<BETA, 16>(m1, m2);
+  if (G > 32) top_cross<BETA, 32>(m1, m2);
+}
+
+// Folds a block's top BETA (m1 > m2) into subrange j of an LDS delegate
+// vector of BETA entries per subrange (zeroed first).  BETA 1: an atomic
+// maximum.  BETA 2: m1 goes into the first entry by an atomic maximum, and
+// the larger of m2 and whichever of m1 and the displaced value is smaller
+// into the second.  Each update of the first entry hands the smaller of its
+// two values to the second, so every value except the overall maximum
+// reaches the second entry once: it ends as the runner-up in any order of
+// updates.
+template <int BETA>
+__device__ __forceinline__ void d_fold(uint64_t* D, uint32_t j, uint64_t m1, uint64_t m2) {
+  if constexpr (BETA == 1) {
+    atomicMax((unsigned long long*)&D[j], (unsigned long long)m1);
+  } else {
+    const uint64_t old = atomicMax((unsigned long long*)&D[2 * j], (unsigned long long)m1);
+    const uint64_t lo = old < m1 ? old : m1;
+    const uint64_t v = lo > m2 ? lo : m2;
+    if (v) atomicMax((unsigned long long*)&D[2 * j + 1], (unsigned long long)v);
+  }
 }
 
 // The keys of one problem behind a raw buffer resource: loads are plain
@@ -486,10 +548,10 @@ __device__ inline void b_radix(const BatchDesc& d, BatchSmem& sm, uint32_t* rec)
 // Delegate vector for subranges of at least 256 keys, over the keys
 // [lo, min(hi, n4)) (lo a multiple of kBStep and of 2^alpha): waves stream
 // them in steps of kBStep with kBU 1 KiB loads in flight; each 256-key block
-// lies inside one subrange, whose delegate (sm.D[s - lo / 2^alpha]) takes the
-// block's maximum by an LDS atomic max (D starts at 0, below every composite
-// of a real element).
-template <bool VEC>
+// lies inside one subrange s, whose BETA entries (from sm.D[(s - lo /
+// 2^alpha) * BETA]) take the block's top BETA by LDS atomics (D starts at 0,
+// below every composite of a real element).
+template <bool VEC, int BETA>
 __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4, uint32_t alpha,
                                         Codec cx, BatchSmem& sm) {
   const uint32_t L = 1u << alpha;
@@ -501,55 +563,52 @@ __device__ inline void b_delegates_wide(const Keys<VEC>& ks, uint32_t lo, uint32
 #pragma unroll
     for (int j = 0; j < kBU; ++j) ks.load4(base + j * 256 + lane * 4, v[j]);
     if (L >= kBStep) {
-      uint64_t m = 0;
+      uint64_t m1 = 0, m2 = 0;
 #pragma unroll
       for (int j = 0; j < kBU; ++j)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(cx.enc(v[j][c]), p);
-          if (p < end && x > m) m = x;
+          top_push<BETA>(m1, m2, p < end ? x : 0ull);
         }
-      m = wave_max64(m);
-      if (lane == 0) atomicMax((unsigned long long*)&sm.D[(base >> alpha) - s0], (unsigned long long)m);
+      group_top<BETA>(m1, m2, 64);
+      if (lane == 0) d_fold<BETA>(sm.D, (base >> alpha) - s0, m1, m2);
     } else {
 #pragma unroll
       for (int j = 0; j < kBU; ++j) {
-        uint64_t m = 0;
+        uint64_t m1 = 0, m2 = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t p = base + j * 256 + lane * 4 + c;
           const uint64_t x = comp(cx.enc(v[j][c]), p);
-          if (p < end && x > m) m = x;
+          top_push<BETA>(m1, m2, p < end ? x : 0ull);
         }
-        m = wave_max64(m);
-        if (lane == 0 && base + j * 256 < end)
-          atomicMax((unsigned long long*)&sm.D[((base + j * 256) >> alpha) - s0], (unsigned long long)m);
+        group_top<BETA>(m1, m2, 64);
+        if (lane == 0 && base + j * 256 < end) d_fold<BETA>(sm.D, ((base + j * 256) >> alpha) - s0, m1, m2);
       }
     }
   }
 }
 
 // The last n mod 4 keys (16-byte loads stop at n4), all in one subrange:
-// one thread folds them into its delegate sm.D[n4 / 2^alpha - s0].
+// one thread folds them into that subrange's delegates (index n4 / 2^alpha - s0).
+template <int BETA>
 __device__ __forceinline__ void b_delegates_tail(const BatchDesc& d, uint32_t n4, uint32_t s0, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n;
   if (threadIdx.x == 0 && n4 < n) {
-    uint64_t m = 0;
-    for (uint32_t i = n4; i < n; ++i) {
-      const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
-      m = x > m ? x : m;
-    }
-    atomicMax((unsigned long long*)&sm.D[(n4 >> d.alpha) - s0], (unsigned long long)m);
+    uint64_t m1 = 0, m2 = 0;
+    for (uint32_t i = n4; i < n; ++i) top_push<BETA>(m1, m2, comp(codec_of(d.dtype).enc(d.keys[i]), i));
+    d_fold<BETA>(sm.D, (n4 >> d.alpha) - s0, m1, m2);
   }
 }
 
 // Delegate vector for subranges of 4..128 keys, over the keys
 // [lo, min(hi, n4)) (lo a multiple of kBStep): each 256-key wave-load holds
 // whole subranges, 2^(alpha-2) lanes each; a segmented butterfly gives each
-// subrange's maximum to its first lane, which stores it as
-// sm.D[s - lo / 2^alpha].
-template <bool VEC>
+// subrange's top BETA to its first lane, which folds them into entries
+// (s - lo / 2^alpha) * BETA.. of sm.D.
+template <bool VEC, int BETA>
 __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4,
                                           uint32_t alpha, Codec cx, BatchSmem& sm) {
   const uint32_t G = 1u << (alpha - 2);  // lanes per subrange
@@ -563,27 +622,26 @@ __device__ inline void b_delegates_narrow(const Keys<VEC>& ks, uint32_t lo, uint
 #pragma unroll
     for (int j = 0; j < kBU; ++j) {
       const uint32_t p = base + j * 256 + lane * 4;
-      uint64_t m = 0;
+      uint64_t m1 = 0, m2 = 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const uint64_t x = comp(cx.enc(v[j][c]), p + c);
-        if (p + c < end && x > m) m = x;
+        top_push<BETA>(m1, m2, p + c < end ? x : 0ull);
       }
-      m = group_max64(m, G);
-      if ((lane & (G - 1)) == 0 && p < end)
-        atomicMax((unsigned long long*)&sm.D[(p >> alpha) - s0], (unsigned long long)m);
+      group_top<BETA>(m1, m2, G);
+      if ((lane & (G - 1)) == 0 && p < end) d_fold<BETA>(sm.D, (p >> alpha) - s0, m1, m2);
     }
   }
 }
 
-// Survivors: every element ranked >= t in the k-1 subranges listed in Q,
-// read as one virtual vector of (k-1) * 2^alpha keys in 4-key pieces (a
-// piece never crosses a subrange).
+// Survivors: every element ranked >= t in the nq subranges listed in Q,
+// read as one virtual vector of nq * 2^alpha keys in 4-key pieces (a piece
+// never crosses a subrange).
 template <bool VEC>
-__device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k, uint32_t alpha, const uint32_t* Q,
+__device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t nq, uint32_t alpha, const uint32_t* Q,
                                    uint64_t t, Codec cx, BatchSmem& sm) {
   const uint32_t L = 1u << alpha;
-  const uint32_t total = (k - 1) << alpha;
+  const uint32_t total = nq << alpha;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   for (uint32_t base = wave * kBStep; base < total; base += kBWaves * kBStep) {
     uint32_t v[kBU][4], pb[kBU];
@@ -608,25 +666,39 @@ __device__ inline void b_survivors(const Keys<VEC>& ks, uint32_t n4, uint32_t k,
 // Everything after the delegate vector: t, the qualifying subranges, the
 // survivors and the output.  sm.D[0..cnt) holds every delegate ranked at or
 // above the k-th (the whole vector, or its top part when a split problem's
-// vector lives in global memory), and sm.tail_del the delegate of the
-// subrange holding the last n mod 4 keys.  False if the survivors overflow
-// LDS (nothing has been written then).
-template <bool VEC>
+// vector lives in global memory), BETA = 2 as (first, second) pairs of one
+// subrange each; sm.tail_del is the last delegate of the subrange holding
+// the last n mod 4 keys.
+//   BETA 1: the k-1 subranges whose delegate ranks above t are re-read.
+//   BETA 2 (Rule 3): a subrange is re-read only if its second delegate ranks
+//     above t (at most (k-1)/2 of them); of any other subrange only its
+//     first delegate can rank above t (every other element is at most its
+//     second delegate, so at most t), and that delegate survives as is.
+// t itself survives once: its subrange is never re-read.  False if the
+// survivors overflow LDS (nothing has been written then).
+template <bool VEC, int BETA>
 __device__ inline bool b_finish(const BatchDesc& d, uint32_t cnt, BatchSmem& sm) {
   const uint32_t n = (uint32_t)d.n, k = d.k, alpha = d.alpha, n4 = vec_end<VEC>(n);
   const Keys<VEC> ks(d.keys, n4);
   const uint64_t t = lds_select(sm.D, cnt, k, sm);  // Rule 2: the k-th delegate
-  // the k-1 subranges whose delegate ranks above t (order irrelevant)
-  uint32_t* Q = sm.hist;
-  if (threadIdx.x == 0) { sm.nq = 0; sm.nsurv = 1; sm.surv[0] = t; }  // t itself: its subrange is not re-read
+  uint32_t* Q = sm.hist;  // the subranges to re-read (order irrelevant)
+  if (threadIdx.x == 0) { sm.nq = 0; sm.nsurv = 1; sm.surv[0] = t; }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cnt; i += kBT) {
-    const uint64_t x = sm.D[i];
-    if (x > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(x) >> alpha;
+  if constexpr (BETA == 1) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBT) {
+      const uint64_t x = sm.D[i];
+      if (x > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(x) >> alpha;
+    }
+  } else {
+    for (uint32_t i = threadIdx.x; i < cnt / 2; i += kBT) {
+      const uint64_t a = sm.D[2 * i], b = sm.D[2 * i + 1];
+      if (b > t) Q[atomicAdd(&sm.nq, 1u)] = comp_pos(b) >> alpha;
+      else if (a > t) sm.surv[atomicAdd(&sm.nsurv, 1u)] = a;  // fewer than k of them
+    }
   }
   __syncthreads();
-  b_survivors<VEC>(ks, n4, k, alpha, Q, t, codec_of(d.dtype), sm);
-  if (threadIdx.x == 0 && n4 < n && sm.tail_del > t) {  // the last keys, when their subrange is listed
+  b_survivors<VEC>(ks, n4, sm.nq, alpha, Q, t, codec_of(d.dtype), sm);
+  if (threadIdx.x == 0 && n4 < n && sm.tail_del > t) {  // the last keys, when their subrange is re-read
     for (uint32_t i = n4; i < n; ++i) {
       const uint64_t x = comp(codec_of(d.dtype).enc(d.keys[i]), i);
       if (x >= t) {
@@ -642,30 +714,40 @@ __device__ inline bool b_finish(const BatchDesc& d, uint32_t cnt, BatchSmem& sm)
   return true;
 }
 
-// The delegate method for one problem in one workgroup; false if the
-// survivors overflow LDS (nothing has been written then).
-template <bool VEC>
-__device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
-  const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
-  const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
-  const Keys<VEC> ks(d.keys, n4);
-  for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = 0;
-  __syncthreads();
-  if (alpha >= 8) b_delegates_wide<VEC>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
-  else b_delegates_narrow<VEC>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
-  b_delegates_tail(d, n4, 0, sm);
-  __syncthreads();
-  if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[n4 >> alpha] : 0;
-  return b_finish<VEC>(d, S, sm);
+template <bool VEC, int BETA>
+__device__ inline void b_delegates(const Keys<VEC>& ks, uint32_t lo, uint32_t hi, uint32_t n4, uint32_t alpha,
+                                   Codec cx, BatchSmem& sm) {
+  if (alpha >= 8) b_delegates_wide<VEC, BETA>(ks, lo, hi, n4, alpha, cx, sm);
+  else b_delegates_narrow<VEC, BETA>(ks, lo, hi, n4, alpha, cx, sm);
 }
 
-// A split problem's delegate vector (S entries, global memory, written by the
-// tiles' workgroups with coherent stores) cut down to LDS: MSD digits of the
-// composites are histogrammed over it until the class holding the k-th
-// delegate plus everything ranked above the class fit sm.D (kBMaxS), then
-// those are copied there (the k-th delegate and all delegates above it among
-// them).  Returns their count, or 0 if no cut fits (massive ties).
+// The delegate method for one problem in one workgroup; false if the
+// survivors overflow LDS (nothing has been written then).
+template <bool VEC, int BETA>
+__device__ inline bool b_delegate(const BatchDesc& d, BatchSmem& sm) {
+  const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
+  const uint32_t E = ((n + (1u << alpha) - 1) >> alpha) * BETA;
+  const Keys<VEC> ks(d.keys, n4);
+  for (uint32_t i = threadIdx.x; i < E; i += kBT) sm.D[i] = 0;
+  __syncthreads();
+  b_delegates<VEC, BETA>(ks, 0, n, n4, alpha, codec_of(d.dtype), sm);
+  b_delegates_tail<BETA>(d, n4, 0, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) sm.tail_del = n4 < n ? sm.D[(n4 >> alpha) * BETA + BETA - 1] : 0;
+  return b_finish<VEC, BETA>(d, E, sm);
+}
+
+// A split problem's delegate vector (S subranges of BETA entries, global
+// memory, written by the tiles' workgroups with coherent stores) cut down to
+// LDS: MSD digits of the composites are histogrammed over it until the
+// class holding the k-th delegate plus everything ranked above the class
+// fit sm.D (kBMaxS entries, counting BETA per such entry), then the
+// subranges whose first delegate lies in that class or above are copied
+// there whole (the k-th delegate and all delegates above it among them).
+// Returns the number of entries copied, or 0 if no cut fits (massive ties).
+template <int BETA>
 __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t k, BatchSmem& sm) {
+  const uint32_t E = S * BETA;
   uint64_t prefix = 0, mask = 0;
   uint32_t r = k, above = 0, cls = 0;
   bool fits = false;
@@ -674,7 +756,7 @@ __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t
     __syncthreads();
     const int sh = pass_shift(p);
     const uint32_t dm = (1u << pass_bits(p)) - 1;
-    for (uint32_t i = threadIdx.x; i < S; i += kBT) {
+    for (uint32_t i = threadIdx.x; i < E; i += kBT) {
       const uint64_t x = ld_coh64(&Dg[i]);
       if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
     }
@@ -686,7 +768,7 @@ __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t
     r = sm.out[1];
     cls = sm.out[3];
     __syncthreads();
-    if (above + cls <= kBMaxS) {
+    if ((above + cls) * BETA <= kBMaxS) {
       fits = true;
       break;
     }
@@ -694,22 +776,28 @@ __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t
   if (!fits) return 0;
   if (threadIdx.x == 0) sm.nq = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < S; i += kBT) {
-    const uint64_t x = ld_coh64(&Dg[i]);
-    if ((x & mask) >= prefix) sm.D[atomicAdd(&sm.nq, 1u)] = x;  // above + cls entries
+  // a subrange's first delegate is its largest: any of its entries in the
+  // class or above puts the first there, so at most above + cls subranges
+  for (uint32_t s = threadIdx.x; s < S; s += kBT) {
+    const uint64_t x = ld_coh64(&Dg[s * BETA]);
+    if ((x & mask) >= prefix) {
+      const uint32_t j = atomicAdd(&sm.nq, 1u);
+      sm.D[j * BETA] = x;
+      if constexpr (BETA == 2) sm.D[j * BETA + 1] = ld_coh64(&Dg[s * BETA + 1]);
+    }
   }
   __syncthreads();
-  const uint32_t cnt = sm.nq;
+  const uint32_t cnt = sm.nq * BETA;
   __syncthreads();
   return cnt;
 }
 
-// Tile `tile` of a split problem (alpha >= 8): this workgroup builds the
+// Tile `tile` of a split problem (alpha >= 4): this workgroup builds the
 // delegates of its tile and publishes them to Dg with coherent stores, then
 // counts itself in; the workgroup that arrives last loads the whole delegate
 // vector and finishes the problem (radix select over the keys if its
 // survivors overflow).  Nobody waits for anybody.
-template <bool VEC>
+template <bool VEC, int BETA>
 __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
                               uint32_t* rec);
 
@@ -720,45 +808,44 @@ __device__ inline void b_problem_v(const BatchDesc& d, BatchSmem& sm, uint32_t* 
     return;
   }
   if (d.alpha >= 2) {
-    const uint64_t S = (d.n + (1ull << d.alpha) - 1) >> d.alpha;
-    if (S <= kBMaxS && S > d.k && b_delegate<VEC>(d, sm)) return;
+    const uint64_t E = ((d.n + (1ull << d.alpha) - 1) >> d.alpha) * d.beta;
+    if (E <= kBMaxS && E > d.k && (d.beta == 2 ? b_delegate<VEC, 2>(d, sm) : b_delegate<VEC, 1>(d, sm))) return;
     __syncthreads();
   }
   b_radix<VEC>(d, sm, rec);
 }
 
-template <bool VEC>
+template <bool VEC, int BETA>
 __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
                               uint32_t* rec) {
   const uint32_t n = (uint32_t)d.n, alpha = d.alpha, n4 = vec_end<VEC>(n);
-  const uint32_t tlog = tile_log(alpha);
+  const uint32_t tlog = tile_log(alpha, BETA);
   const uint32_t lo = tile << tlog;
   const uint32_t hi = n - lo > (1u << tlog) ? lo + (1u << tlog) : n;
   const uint32_t s0 = lo >> alpha;
-  const uint32_t ns = ((hi - lo) + (1u << alpha) - 1) >> alpha;  // subranges of this tile
+  const uint32_t ne = (((hi - lo) + (1u << alpha) - 1) >> alpha) * BETA;  // entries of this tile
   const Keys<VEC> ks(d.keys, n4);
-  for (uint32_t i = threadIdx.x; i < ns; i += kBT) sm.D[i] = 0;
+  for (uint32_t i = threadIdx.x; i < ne; i += kBT) sm.D[i] = 0;
   __syncthreads();
-  if (alpha >= 8) b_delegates_wide<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
-  else b_delegates_narrow<VEC>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
-  if (hi == n) b_delegates_tail(d, n4, s0, sm);
+  b_delegates<VEC, BETA>(ks, lo, hi, n4, alpha, codec_of(d.dtype), sm);
+  if (hi == n) b_delegates_tail<BETA>(d, n4, s0, sm);
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < ns; i += kBT) st_coh64(&Dg[d.doff + s0 + i], sm.D[i]);
+  for (uint32_t i = threadIdx.x; i < ne; i += kBT) st_coh64(&Dg[d.doff + s0 * BETA + i], sm.D[i]);
   __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
   __syncthreads();
   if (threadIdx.x == 0) sm.item = atomicAdd(arrive, 1u) == d.tiles - 1 ? 1u : 0u;
   __syncthreads();
   if (!sm.item) return;
   const uint32_t S = (n + (1u << alpha) - 1) >> alpha;
-  if (threadIdx.x == 0) sm.tail_del = n4 < n ? ld_coh64(&Dg[d.doff + (n4 >> alpha)]) : 0;
-  uint32_t cnt = S;
-  if (S <= kBMaxS) {
-    for (uint32_t i = threadIdx.x; i < S; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
+  if (threadIdx.x == 0) sm.tail_del = n4 < n ? ld_coh64(&Dg[d.doff + (n4 >> alpha) * BETA + BETA - 1]) : 0;
+  uint32_t cnt = S * BETA;
+  if (cnt <= kBMaxS) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
     __syncthreads();
   } else {
-    cnt = b_cut_global(Dg + d.doff, S, d.k, sm);
+    cnt = b_cut_global<BETA>(Dg + d.doff, S, d.k, sm);
   }
-  if (cnt && b_finish<VEC>(d, cnt, sm)) return;
+  if (cnt && b_finish<VEC, BETA>(d, cnt, sm)) return;
   __syncthreads();
   b_radix<VEC>(d, sm, rec);
 }
@@ -772,8 +859,13 @@ __device__ inline void b_problem(const BatchDesc& d, BatchSmem& sm, uint32_t* re
 __device__ inline void b_tile_any(const BatchDesc& d, uint32_t tile, uint32_t* arrive, uint64_t* Dg, BatchSmem& sm,
                                   uint32_t* rec) {
   const bool vec = (reinterpret_cast<uintptr_t>(d.keys) & 15u) == 0;
-  if (vec) b_tile<true>(d, tile, arrive, Dg, sm, rec);
-  else b_tile<false>(d, tile, arrive, Dg, sm, rec);
+  if (d.beta == 2) {
+    if (vec) b_tile<true, 2>(d, tile, arrive, Dg, sm, rec);
+    else b_tile<false, 2>(d, tile, arrive, Dg, sm, rec);
+  } else {
+    if (vec) b_tile<true, 1>(d, tile, arrive, Dg, sm, rec);
+    else b_tile<false, 1>(d, tile, arrive, Dg, sm, rec);
+  }
 }
 
 // Work items (problem << 8 | tile), claimed from *counter (starts at 0):

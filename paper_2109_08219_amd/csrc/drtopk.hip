@@ -91,7 +91,7 @@ bool tune_lookup(int form, uint64_t n, uint32_t k, int* alpha, int* beta) {
   return false;
 }
 
-int batched_alpha(uint64_t n, uint32_t k);
+int batched_alpha(uint64_t n, uint32_t k, int* beta = nullptr);
 bool batched_eligible(uint64_t n, uint32_t k);
 
 // Problems up to this size (and k <= kBMaxK) finish faster in one workgroup
@@ -113,7 +113,7 @@ int make_plan(const void* keys, uint64_t n, uint32_t k, int dt, const drtopk_opt
     if (n <= kOneWgMaxN && batched_eligible(n, k) && !(k == 1 && n > (1u << 14))) mode = 3;
     else mode = (n <= (uint64_t)kSmallCap || (uint64_t)k * 16 > n) ? 2 : 1;
   }
-  if (mode == 3) p.alpha = batched_alpha(n, k);
+  if (mode == 3) p.alpha = batched_alpha(n, k, &p.beta);
   p.mode = mode;
   p.variant = opt ? opt->variant : 0;
   if (p.variant < 0 || p.variant > 3) return DRTOPK_EINVAL;
@@ -374,7 +374,8 @@ int enqueue_plan(const Plan& p, const void* keys, void* ws, void* out_vals, uint
     d.n = p.n;
     d.k = p.k;
     d.dtype = (uint32_t)dt_code(p.dt);
-    d.alpha = (uint32_t)p.alpha;
+    d.alpha = (uint16_t)p.alpha;
+    d.beta = (uint16_t)p.beta;
     d.out_vals = kth_only ? nullptr : static_cast<uint32_t*>(out_vals);
     d.out_idx = kth_only ? nullptr : out_idx;
     d.out_kth = static_cast<uint32_t*>(out_kth);
@@ -471,11 +472,15 @@ int fill_stats_wide(const WPlan& p, void* ws, hipStream_t s, drtopk_stats_t* sta
 
 // Subrange exponent of a problem taken by the batched workgroup kernel; 0 =
 // sorted outright (n <= kBSmallN) or radix select without delegates.
-int batched_alpha(uint64_t n, uint32_t k) {
+// *beta (if given): delegates per subrange, 1 unless a table entry asks for 2.
+int batched_alpha(uint64_t n, uint32_t k, int* beta) {
+  if (beta) *beta = 1;
   if (n <= kBSmallN) return 0;
-  auto subranges = [n](int a) { return (n + (1ull << a) - 1) >> a; };
   int a = -1, b = 0;
   if (tune_lookup(DRTOPK_FORM_BATCHED, n, k, &a, &b) && a == 0) return 0;  // measured: radix select
+  const uint64_t bt = b == 2 ? 2 : 1;
+  auto entries = [n, bt](int a) { return ((n + (1ull << a) - 1) >> a) * bt; };
+  int r = 0;
   if (n > (1ull << kBTileLog)) {
     // split across workgroups: the delegate vector lives in global memory, so
     // it may hold up to kBMaxSG entries and Rule 4's shorter subranges apply
@@ -484,21 +489,24 @@ int batched_alpha(uint64_t n, uint32_t k) {
     if (a < 0) a = rule_alpha(n, k);
     if (a < 4) a = 4;
     if (a > 24) a = 24;
-    while (a < 24 && subranges(a) > kBMaxSG) ++a;
-    while (subranges(a) < 2ull * k && a > 4 && subranges(a - 1) <= kBMaxSG) --a;
-    return subranges(a) > k ? a : 0;
+    while (a < 24 && entries(a) > kBMaxSG) ++a;
+    while (entries(a) < 2ull * k && a > 4 && entries(a - 1) <= kBMaxSG) --a;
+    r = entries(a) > k ? a : 0;
+  } else {
+    if (a < 0) {
+      a = rule_alpha(n, k);
+      if (a < 8) a = 8;  // a wave reads 256 keys per step: shorter subranges idle lanes
+    }
+    if (a > 24) a = 24;
+    if (a < 2) a = 2;
+    while (a < 24 && entries(a) > kBMaxS) ++a;  // delegate vector fits the LDS
+    // at least 2k delegates where the LDS allows: with t the k-th of S subrange
+    // maxima, about -S ln(1 - k/S) <= 0.7 S elements survive, within capacity
+    while (entries(a) < 2ull * k && a > 2 && entries(a - 1) <= kBMaxS) --a;
+    r = entries(a) > k && entries(a) <= kBMaxS ? a : 0;
   }
-  if (a < 0) {
-    a = rule_alpha(n, k);
-    if (a < 8) a = 8;  // a wave reads 256 keys per step: shorter subranges idle lanes
-  }
-  if (a > 24) a = 24;
-  if (a < 2) a = 2;
-  while (a < 24 && subranges(a) > kBMaxS) ++a;  // delegate vector fits the LDS
-  // at least 2k delegates where the LDS allows: with t the k-th of S subrange
-  // maxima, about -S ln(1 - k/S) <= 0.7 S elements survive, within capacity
-  while (subranges(a) < 2ull * k && a > 2 && subranges(a - 1) <= kBMaxS) --a;
-  return subranges(a) > k && subranges(a) <= kBMaxS ? a : 0;
+  if (beta && r) *beta = (int)bt;
+  return r;
 }
 
 bool batched_eligible(uint64_t n, uint32_t k) { return n <= kBMaxN && k <= kBMaxK; }
@@ -513,7 +521,9 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
   d.n = q.n;
   d.k = q.k;
   d.dtype = (uint32_t)dt_code((int)q.dtype);
-  d.alpha = (uint32_t)batched_alpha(q.n, q.k);
+  int beta = 1;
+  d.alpha = (uint16_t)batched_alpha(q.n, q.k, &beta);
+  d.beta = (uint16_t)beta;
   d.out_vals = static_cast<uint32_t*>(q.out_vals);
   d.out_idx = q.out_idx;
   d.out_kth = static_cast<uint32_t*>(q.out_kth);
@@ -525,7 +535,7 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
 // workgroups stream them (their subranges hold at least 16 keys).
 uint32_t batched_tiles(const BatchDesc& d) {
   if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 4) return 1;
-  const uint32_t tlog = tile_log(d.alpha);
+  const uint32_t tlog = tile_log(d.alpha, d.beta);
   return (uint32_t)((d.n + (1ull << tlog) - 1) >> tlog);
 }
 
@@ -546,7 +556,7 @@ int launch_batched(const std::vector<const drtopk_problem_t*>& items, hipStream_
     if (descs[i].tiles > 1) {
       split = true;
       descs[i].doff = dg_entries;
-      dg_entries += (descs[i].n + (1ull << descs[i].alpha) - 1) >> descs[i].alpha;
+      dg_entries += ((descs[i].n + (1ull << descs[i].alpha) - 1) >> descs[i].alpha) * descs[i].beta;
     }
     nwork += descs[i].tiles;
   }
@@ -693,9 +703,9 @@ int fill_stats(const Plan& p, void* ws, hipStream_t s, drtopk_stats_t* stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->mode = 3;
     stats->alpha = p.alpha;
-    stats->beta = 1;
+    stats->beta = p.alpha ? p.beta : 1;
     stats->subranges = p.alpha ? (p.n + (1ull << p.alpha) - 1) >> p.alpha : 0;
-    stats->delegates = stats->subranges;
+    stats->delegates = stats->subranges * (uint64_t)stats->beta;
     return DRTOPK_OK;
   }
   Ctl h;
@@ -852,9 +862,11 @@ int drtopk_footprint(uint64_t n, uint32_t k, int dtype, uint64_t* bytes) {
     BatchDesc d{};
     d.n = n;
     d.k = k;
-    d.alpha = (uint32_t)batched_alpha(n, k);
+    int beta = 1;
+    d.alpha = (uint16_t)batched_alpha(n, k, &beta);
+    d.beta = (uint16_t)beta;
     d.tiles = batched_tiles(d);
-    if (d.tiles > 1) ws += 4ull * d.tiles + 8ull * ((n + (1ull << d.alpha) - 1) >> d.alpha);
+    if (d.tiles > 1) ws += 4ull * d.tiles + 8ull * beta * ((n + (1ull << d.alpha) - 1) >> d.alpha);
   }
   *bytes = 4 * n + 8ull * k + 4 + ws;
   return DRTOPK_OK;
@@ -887,15 +899,17 @@ int drtopk_tune_get(drtopk_tune_t* out, uint32_t cap, uint32_t* count) {
   return DRTOPK_OK;
 }
 
-int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha) {
+int drtopk_batched_alpha(uint64_t n, uint32_t k, int32_t* route, int32_t* alpha, int32_t* beta) {
   if (!route || !alpha || n == 0 || n >= (1ull << 32) || k == 0 || k > n) return DRTOPK_EINVAL;
+  int b = 1;
   if (!batched_eligible(n, k)) {
     *route = 0;
     *alpha = 0;
   } else {
-    *alpha = batched_alpha(n, k);
+    *alpha = batched_alpha(n, k, &b);
     *route = n <= kBSmallN ? 1 : *alpha ? 2 : 3;
   }
+  if (beta) *beta = b;
   return DRTOPK_OK;
 }
 

@@ -81,7 +81,7 @@ struct Ctl {
   uint32_t nw;    // W fill level
   uint32_t selpub[8];  // selection state published between tail phases (W: 0..3, survivors: 4..7)
   uint32_t uniq_idx;  // position of a unique entry found by a tail pass
-  uint32_t tpub[2];   // threshold t published by block 0 of the tail (coherent stores)
+  uint32_t tpub[4];   // threshold t' and its bin, published by block 0 of the tail (coherent stores)
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
   uint64_t max1;  // largest delegate composite = largest element (the k = 1 answer)
   // bucket select (tail variant 3), [0] over the delegates, [1] over the survivors

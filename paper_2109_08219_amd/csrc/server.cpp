@@ -280,7 +280,7 @@ int submit_at(drtopk_server_t* s, const drtopk_problem_t* req, Clock::time_point
   if (st) return st;
   if (!req->keys) return DRTOPK_EINVAL;
   int32_t route = 0, alpha = 0;
-  st = drtopk_batched_alpha(req->n, req->k, &route, &alpha);
+  st = drtopk_batched_alpha(req->n, req->k, &route, &alpha, nullptr);
   if (st) return st;
   Req r;
   r.p = *req;

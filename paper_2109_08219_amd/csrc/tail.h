@@ -227,19 +227,26 @@ __device__ __forceinline__ uint64_t get64(const uint32_t* p) {
 // ---- multi-block radix select over a buffer written earlier in this kernel --
 // Phases ph[0..kPasses): one per digit.  Returns the rank-th largest composite
 // of (key[i], idx[i]), i < count, identically in every block.
+//   key_known: the sought entry's key is key0 and `rank` counts from the
+//     largest entry with that key; the three key digits are skipped.
+//   bound: a lower bound suffices: once the class holding the rank has a
+//     single member (the sought entry), its prefix with the remaining bits
+//     zero is returned; exactly the same entries rank at or above it.
 constexpr uint32_t kSelChunk = kTailThreads * 8;
 
 __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t rank,
                                        uint32_t (*hist)[kBins], Phase* ph, uint32_t* pubsel, Ctl* ctl,
-                                       TailSmem& sm) {
-  uint64_t prefix = 0, mask = 0;
+                                       TailSmem& sm, bool key_known = false, uint32_t key0 = 0,
+                                       bool bound = false) {
+  uint64_t prefix = key_known ? (uint64_t)key0 << 32 : 0ull;
+  uint64_t mask = key_known ? 0xFFFFFFFF00000000ull : 0ull;
   uint32_t r = rank;
   const uint32_t nchunks = (count + kSelChunk - 1) / kSelChunk;
   if (nchunks == 0 || rank == 0 || rank > count) {  // inconsistent input: flag, never wait
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_err(ctl, ERR_SELECT);
     return 0;
   }
-  for (int p = 0; p < kPasses; ++p) {
+  for (int p = key_known ? 3 : 0; p < kPasses; ++p) {
     for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
     const int sh = pass_shift(p);
     const uint32_t dm = (1u << pass_bits(p)) - 1;
@@ -277,6 +284,7 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
         if (!sm.out[2]) flag_err(ctl, ERR_SELECT);
         pub64(pubsel, prefix | ((uint64_t)sm.out[0] << sh));
         st_coh(pubsel + 2, sm.out[1]);
+        st_coh(pubsel + 3, sm.out[3]);
       }
       if (threadIdx.x == 0) ctl->tstamp[(ph - ctl->ph) + p] = __builtin_amdgcn_s_memrealtime();
       raise_ready(&ph[p]);
@@ -285,7 +293,9 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
     prefix = get64(pubsel);
     mask |= (uint64_t)dm << sh;
     r = ld_coh(pubsel + 2);
+    const uint32_t members = ld_coh(pubsel + 3);
     __syncthreads();
+    if (bound && members == 1u) break;  // uniform: every block read the same word
   }
   return prefix;
 }
@@ -741,6 +751,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     uint64_t m = (uint64_t)a.kD - ctl->cut_rank + ctl->cut_count;
     const bool refine = hi > lo && (m > limit || ctl->cut_count > (crowd > 256u ? crowd : 256u));
     uint32_t tkey = lo;
+    // the bin (or sub-bin) holding t: its key range and t's rank inside it
+    uint32_t bhi = hi, brank = ctl->cut_rank;
     if (refine) {
       const uint32_t fsh = bitlen32(hi - lo) > 11u ? bitlen32(hi - lo) - 11u : 0u;
       for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
@@ -770,8 +782,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
           // padding entries (key 0) were left out of the sub-bins; if that leaves
           // the rank unreached, keep the whole bin
           const bool ok = sm.out[2] != 0;
-          st_coh(&ctl->tpub[0], ok ? lo + (sm.out[0] << fsh) : lo);
+          const uint32_t sublo = lo + (sm.out[0] << fsh);
+          const uint32_t subhi = hi - sublo > (1u << fsh) - 1u ? sublo + ((1u << fsh) - 1u) : hi;
+          st_coh(&ctl->tpub[0], ok ? sublo : lo);
           st_coh(&ctl->tpub[1], ok ? a.kD - sm.out[1] + sm.out[3] : (uint32_t)(m < 0xFFFFFFFFull ? m : 0xFFFFFFFFull));
+          st_coh(&ctl->tpub[2], ok ? subhi : hi);
+          st_coh(&ctl->tpub[3], ok ? sm.out[1] : ctl->cut_rank);
         }
         stamp(ctl, PH_H);
         raise_ready(&ph[PH_H]);
@@ -779,11 +795,18 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       wait_ready(&ph[PH_H], ctl);
       tkey = ld_coh(&ctl->tpub[0]);
       m = ld_coh(&ctl->tpub[1]);
+      bhi = ld_coh(&ctl->tpub[2]);
+      brank = ld_coh(&ctl->tpub[3]);
     }
     if (m <= limit) {
       T = (uint64_t)tkey << 32;
     } else {
-      T = tail_select(a.dkey, a.didx, (uint32_t)a.nd, a.kD, ctl->histW, &ph[PH_DSEL], ctl->selpub, ctl, sm);
+      // massive ties: the exact select, from the position digits on when the
+      // bin holds a single key, stopping once t's class has one member (any
+      // T <= t with the same delegates at or above it serves Rule 2)
+      const bool one_key = tkey == bhi;
+      T = tail_select(a.dkey, a.didx, (uint32_t)a.nd, one_key ? brank : a.kD, ctl->histW, &ph[PH_DSEL],
+                      ctl->selpub, ctl, sm, one_key, tkey, true);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->selD.prefix = T;  // host statistics

@@ -4,10 +4,11 @@ Batched form:
 For every bucket (floor(log2 n), floor(log2 k)) that the batched kernel owns,
 a batch of synthetic problems of that bucket (half uint32 uniform, half
 float32 normal, lengths and k uniform inside the bucket) is timed with each
-candidate alpha: Rule 4's value and its neighbours, as the kernel would
-actually run them (raised to fit its delegate vector, lowered to keep more
-delegates than k), the workgroup radix select without delegates
-(written as alpha 0), and no entry (Rule 4 itself); each is timed twice,
+candidate (alpha, beta): Rule 4's alpha and its neighbours with one or two
+delegates per subrange, as the kernel would actually run them (raised to
+fit its delegate vector, lowered to keep more delegates than k), the
+workgroup radix select without delegates (written as alpha 0), and no
+entry (Rule 4 itself, beta 1); each is timed twice,
 interleaved, keeping the faster run.  A bucket gets an entry only when an
 alternative beats Rule 4.  The table is written to tuning.json,
 which the binding loads when it opens the library.  Every alpha gives the
@@ -77,31 +78,34 @@ def tune_batched(drt, torch, problems, reps, log=print):
                 continue
             # the alpha the kernel runs for a problem of this bucket under a table entry a
             rep_n, rep_k = probs[0][0].numel(), probs[0][1]
-            base = drt.batched_route(rep_n, rep_k)
+            base = drt.batched_plan(rep_n, rep_k)
             if base[0] != 2:
                 continue
             cands = {}
-            for a in range(max(2, base[1] - 3), min(24, base[1] + 3) + 1):
-                drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, a, 1)])
-                r, eff = drt.batched_route(rep_n, rep_k)
-                if r == 2 and eff != base[1]:  # Rule 4's own alpha is the "rule" candidate
-                    cands.setdefault(eff, a)
+            for b in (1, 2):
+                for a in range(max(2, base[1] - 3), min(24, base[1] + 3) + 1):
+                    drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, a, b)])
+                    r, eff, beff = drt.batched_plan(rep_n, rep_k)
+                    if r == 2 and (eff, beff) != base[1:]:  # Rule 4's own plan is the "rule" candidate
+                        cands.setdefault((eff, beff), (a, b))
             batch = drt.Batch(probs)
-            # candidates: table entries (alpha as requested; 0 = radix select) and no entry (Rule 4),
-            # each timed twice, interleaved, keeping the faster run
-            options = [("rule", None)] + [(f"a{eff}", a) for eff, a in sorted(cands.items())] + [("radix", 0)]
+            # candidates: table entries ((alpha, beta) as requested; alpha 0 = radix select) and no
+            # entry (Rule 4, beta 1), each timed twice, interleaved, keeping the faster run
+            options = ([("rule", None)] + [(f"a{eff}b{beff}", ab) for (eff, beff), ab in sorted(cands.items())]
+                       + [("radix", (0, 1))])
             times = {}
             for _ in range(2):
-                for name, a in options:
-                    drt.tune_set([] if a is None else [(drt.FORM_BATCHED, lg_n, lg_k, a, 1)])
+                for name, ab in options:
+                    drt.tune_set([] if ab is None else [(drt.FORM_BATCHED, lg_n, lg_k, ab[0], ab[1])])
                     t = _time(torch, batch, reps)
                     times[name] = min(times.get(name, t), t)
             drt.tune_set([])
             best = min(times, key=times.get)
-            a_best = dict(options)[best]
-            if a_best is not None:  # no entry when Rule 4 is the fastest
-                entries.append({"form": drt.FORM_BATCHED, "lg_n": lg_n, "lg_k": lg_k, "alpha": a_best, "beta": 1,
-                                "ms": round(times[best], 4), "rule_alpha": base[1], "rule_ms": round(times["rule"], 4)})
+            ab_best = dict(options)[best]
+            if ab_best is not None:  # no entry when Rule 4 is the fastest
+                entries.append({"form": drt.FORM_BATCHED, "lg_n": lg_n, "lg_k": lg_k, "alpha": ab_best[0],
+                                "beta": ab_best[1], "ms": round(times[best], 4), "rule_alpha": base[1],
+                                "rule_ms": round(times["rule"], 4)})
             log(f"n~2^{lg_n} k~2^{lg_k}: rule alpha {base[1]} {times['rule']:.3f} ms, best {best} "
                 f"{times[best]:.3f} ms  " + " ".join(f"{nm}:{t:.3f}" for nm, t in times.items()))
             del batch, probs

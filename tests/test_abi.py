@@ -220,11 +220,26 @@ def test_batched_routes_without_gpu():
         drt.tune_set([(drt.FORM_BATCHED, 16, 10, 16, 1)])
         r, a = drt.batched_route(1 << 16, 1024)
         assert r == 2 and -(-(1 << 16) // (1 << a)) > 1024  # lowered until S > k
+        # beta 2 from the table: the delegate vector holds 2S entries, within the same bounds
+        for lg_n, lg_k in ((16, 5), (20, 10), (22, 11), (13, 0)):
+            n, k = 1 << lg_n, 1 << lg_k
+            drt.tune_set([(drt.FORM_BATCHED, lg_n, lg_k, 6, 2)])
+            r, a, b = drt.batched_plan(n, k)
+            E = 2 * -(-n // (1 << a))
+            assert r == 2 and b == 2 and k < E <= (32768 if n > (1 << 18) else 4096), (lg_n, lg_k, a, b)
+        drt.tune_set([(drt.FORM_BATCHED, 20, 10, 6, 4)])  # only 1 and 2 run in the workgroup
+        assert drt.batched_plan(1 << 20, 1024)[2] == 1
+        drt.tune_set([(drt.FORM_BATCHED, 20, 10, 0, 2)])  # alpha 0: radix select, no delegates
+        assert drt.batched_plan(1 << 20, 1024) == (3, 0, 1)
+        drt.tune_set([])
+        assert drt.batched_plan(1 << 20, 1024) == (2, 6, 1)
         L = drt.lib()
-        r, al = ctypes.c_int32(), ctypes.c_int32()
-        assert L.drtopk_batched_alpha(0, 1, ctypes.byref(r), ctypes.byref(al)) == 1
-        assert L.drtopk_batched_alpha(10, 11, ctypes.byref(r), ctypes.byref(al)) == 1
-        assert L.drtopk_batched_alpha(10, 1, None, ctypes.byref(al)) == 1
+        r, al, be = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert L.drtopk_batched_alpha(0, 1, ctypes.byref(r), ctypes.byref(al), None) == 1
+        assert L.drtopk_batched_alpha(10, 11, ctypes.byref(r), ctypes.byref(al), None) == 1
+        assert L.drtopk_batched_alpha(10, 1, None, ctypes.byref(al), None) == 1
+        assert L.drtopk_batched_alpha(10, 1, ctypes.byref(r), ctypes.byref(al), ctypes.byref(be)) == 0
+        assert (r.value, al.value, be.value) == (1, 0, 1)
     finally:
         drt.tune_set(saved)
 
@@ -248,6 +263,15 @@ def test_server_and_footprint_arguments_without_gpu():
     # a batched problem split across workgroups also holds its global delegate vector
     r, a = drt.batched_route(1 << 20, 1000)
     assert drt.footprint(1 << 20, 1000) == 4 * (1 << 20) + 8004 + 80 + 4 * 4 + 8 * ((1 << 20) >> a)
+    saved = drt.tune_get()
+    try:  # beta 2: twice the entries, tiles of half the keys
+        drt.tune_set([(drt.FORM_BATCHED, 20, 9, 6, 2)])
+        r, a, b = drt.batched_plan(1 << 20, 1000)
+        assert (r, a, b) == (2, 6, 2)
+        tiles = (1 << 20) >> 17
+        assert drt.footprint(1 << 20, 1000) == 4 * (1 << 20) + 8004 + 80 + 4 * tiles + 16 * ((1 << 20) >> a)
+    finally:
+        drt.tune_set(saved)
     assert drt.footprint(1 << 24, 100) > 4 * (1 << 24) + 804
     b = ctypes.c_uint64()
     assert L.drtopk_footprint(10, 11, 0, ctypes.byref(b)) == 1

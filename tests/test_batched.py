@@ -119,8 +119,9 @@ def test_each_route():
     check_batch(hosts, b, "routes")
 
 
+@pytest.mark.parametrize("beta", [1, 2])
 @pytest.mark.parametrize("alpha", [2, 3, 5, 8, 9, 11, 13, 16])
-def test_tuned_alpha_is_exact(alpha):
+def test_tuned_alpha_is_exact(alpha, beta):
     """Any table entry gives the same (exact) results: the kernel only raises
     alpha to fit its delegate vector or lowers it to keep more delegates than k."""
     hosts = []
@@ -131,11 +132,14 @@ def test_tuned_alpha_is_exact(alpha):
     entries = []
     for x, dt, k in hosts:
         lg_n, lg_k = int(np.log2(x.shape[0])), int(np.log2(k))
-        entries.append((drt.FORM_BATCHED, lg_n, lg_k, alpha, 1))
+        entries.append((drt.FORM_BATCHED, lg_n, lg_k, alpha, beta))
     drt.tune_set(entries)
-    say("tuned alpha", alpha)
+    for x, dt, k in hosts:
+        r, _, b = drt.batched_plan(x.shape[0], k)
+        assert r != 2 or b == beta
+    say("tuned alpha", alpha, "beta", beta)
     b = run_batch(hosts)
-    check_batch(hosts, b, f"alpha {alpha}")
+    check_batch(hosts, b, f"alpha {alpha} beta {beta}")
 
 
 def test_batched_equals_single_bitwise():
@@ -199,18 +203,61 @@ def test_full_workload_4096():
     check_batch(hosts, b, "full")
 
 
-def test_split_problems():
+def beta2_table():
+    """Rule 4's alpha for every bucket the batched kernel owns, with two
+    delegates per subrange."""
+    drt.tune_set([])
+    entries = []
+    for lg_n in range(12, 23):
+        for lg_k in range(0, 12):
+            n, k = max(1 << lg_n, 4097), 1 << lg_k  # n = 2^12 itself is sorted outright
+            if k > n:
+                continue
+            r, a, _ = drt.batched_plan(n, k)
+            if r == 2:
+                entries.append((drt.FORM_BATCHED, lg_n, lg_k, a, 2))
+    return entries
+
+
+def test_beta2_workload_exact():
+    """Two delegates per subrange (Rule 3) in every bucket of the workload:
+    exact, and bit for bit what single calls give (problems of at most 2^16
+    keys take the one-workgroup path there, with the same beta)."""
+    drt.tune_set(beta2_table())
+    hosts = workload_hosts(1024, 4321)
+    n2 = sum(drt.batched_plan(x.shape[0], k)[2] == 2 for x, _, k in hosts)
+    assert n2 > len(hosts) // 2, n2
+    say("beta 2 workload", len(hosts), "with beta 2:", n2)
+    b = run_batch(hosts)
+    check_batch(hosts, b, "beta 2")
+    for i, (x, dt, k) in enumerate(hosts[:: 16]):
+        t = dev(x)
+        v, ix, st = drt.topk_select(t, k, stats=True, check=True)
+        torch.cuda.synchronize()
+        r, a, beta = drt.batched_plan(x.shape[0], k)
+        if st.mode == 3 and st.alpha:
+            assert (st.alpha, st.beta, st.delegates) == (a, beta, beta * st.subranges)
+        check_exact(x, k, dt, to_np(v), to_np(ix), f"beta 2 single n={x.shape[0]} k={k}")
+    say("beta 2 unaligned + k only")
+    b = run_batch(hosts[:200], offsets=[1 + (i % 3) for i in range(200)])
+    check_batch(hosts[:200], b, "beta 2 unaligned")
+    b = run_batch(hosts[:200], kth_only=True)
+    check_batch(hosts[:200], b, "beta 2 k only")
+
+
+@pytest.mark.parametrize("beta", [1, 2])
+def test_split_problems(beta):
     """Problems above 2^18 keys on the delegate route: several workgroups build
     the delegate vector, the last to arrive finishes.  Ragged tails, unaligned
     views, k-only outputs, adversarial inputs (survivor overflow after the
     split) and repeated launches (the arrival counters restart at zero)."""
-    drt.tune_set([])
+    drt.tune_set(beta2_table() if beta == 2 else [])
     hosts = []
     for i, (n, k) in enumerate([((1 << 18) + 1, 1), ((1 << 18) + 3, 7), ((1 << 19) + 2, 500), ((1 << 20) + 7, 2048),
                                 ((1 << 22) - 1, 1000), (1 << 22, 1), (3 << 19, 64)]):
         for kind in ("uniform_u32", "normal_f32"):
             x, dt = synth.keys(kind, n, 800 + 2 * i + (kind == "normal_f32"))
-            assert drt.batched_route(n, k)[0] == 2
+            assert drt.batched_plan(n, k)[::2] == (2, beta)
             hosts.append((x, dt, k))
     for kind in ("sorted_f32", "heavydup_u32"):
         x, dt = synth.keys(kind, (1 << 20) + 5, 901)
