@@ -82,6 +82,8 @@ struct Ctl {
   uint32_t selpub[8];  // selection state published between tail phases (W: 0..3, survivors: 4..7)
   uint32_t uniq_idx;  // position of a unique entry found by a tail pass
   uint32_t tpub[4];   // threshold t' and its bin, published by block 0 of the tail (coherent stores)
+  uint32_t rkmax;     // refinement: largest delegate key in the cut bin
+  uint32_t rknmin;    // refinement: complement of the smallest delegate key in the cut bin
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
   uint64_t max1;  // largest delegate composite = largest element (the k = 1 answer)
   // bucket select (tail variant 3), [0] over the delegates, [1] over the survivors

@@ -229,10 +229,12 @@ __device__ __forceinline__ uint64_t get64(const uint32_t* p) {
 // of (key[i], idx[i]), i < count, identically in every block.
 //   key_known: the sought entry's key is key0 and `rank` counts from the
 //     largest entry with that key; the three key digits are skipped.
-//   bound: a lower bound suffices: once the class holding the rank has a
-//     single member (the sought entry), its prefix with the remaining bits
-//     zero is returned; exactly the same entries rank at or above it.
+//   bound: a lower bound suffices: once the class holding the rank has at
+//     most kBoundTol members below the sought entry, its prefix with the
+//     remaining bits zero is returned; the entries ranked at or above it are
+//     those at or above the sought entry plus at most kBoundTol more.
 constexpr uint32_t kSelChunk = kTailThreads * 8;
+constexpr uint32_t kBoundTol = 64;
 
 __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx, uint32_t count, uint32_t rank,
                                        uint32_t (*hist)[kBins], Phase* ph, uint32_t* pubsel, Ctl* ctl,
@@ -295,7 +297,7 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
     r = ld_coh(pubsel + 2);
     const uint32_t members = ld_coh(pubsel + 3);
     __syncthreads();
-    if (bound && members == 1u) break;  // uniform: every block read the same word
+    if (bound && members - r <= kBoundTol) break;  // uniform: every block read the same words
   }
   return prefix;
 }
@@ -758,6 +760,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
       const uint32_t nchunks = (uint32_t)((a.nd + kWChunk - 1) / kWChunk);
       uint32_t mine = 0;
+      uint32_t kmx = 0, knm = 0;  // largest key in the bin, complement of the smallest
       for (;;) {
         const uint32_t c = claim(&ph[PH_H], nchunks, sm);
         if (c >= nchunks) break;
@@ -766,27 +769,55 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
           const uint64_t i = (uint64_t)c * kWChunk + j + threadIdx.x;
           if (i < a.nd) {
             const uint32_t kk = a.dkey[i];
-            if (kk >= lo && kk <= hi && a.didx[i] != kInvalid) atomicAdd(&sm.u.st.hist[(kk - lo) >> fsh], 1u);
+            if (kk >= lo && kk <= hi && a.didx[i] != kInvalid) {
+              atomicAdd(&sm.u.st.hist[(kk - lo) >> fsh], 1u);
+              kmx = kk > kmx ? kk : kmx;
+              knm = ~kk > knm ? ~kk : knm;
+            }
           }
         }
       }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t x = (uint32_t)__shfl_xor((int)kmx, o), y = (uint32_t)__shfl_xor((int)knm, o);
+        kmx = x > kmx ? x : kmx;
+        knm = y > knm ? y : knm;
+      }
+      if (lane_id() == 0) {
+        sm.rwave[threadIdx.x >> 6] = kmx;
+        sm.rwave[kTailThreads / 64 + (threadIdx.x >> 6)] = knm;
+      }
       __syncthreads();
-      if (mine)
+      if (mine) {
         for (int i = threadIdx.x; i < kBins; i += kTailThreads) {
           const uint32_t v = sm.u.st.hist[i];
           if (v) atomicAdd(&ctl->histH[i], v);
         }
+        if (threadIdx.x == 0) {
+          for (int w = 0; w < kTailThreads / 64; ++w) {
+            kmx = sm.rwave[w] > kmx ? sm.rwave[w] : kmx;
+            knm = sm.rwave[kTailThreads / 64 + w] > knm ? sm.rwave[kTailThreads / 64 + w] : knm;
+          }
+          atomicMax(&ctl->rkmax, kmx);
+          atomicMax(&ctl->rknmin, knm);
+        }
+      }
       if (report(&ph[PH_H], mine, nchunks, sm)) {
         tail_bucket(ctl->histH, ctl->cut_rank, sm.scan, sm.out);
         if (threadIdx.x == 0) {
           // padding entries (key 0) were left out of the sub-bins; if that leaves
-          // the rank unreached, keep the whole bin
+          // the rank unreached, keep the whole bin.  The key range is then cut
+          // to the delegate keys present in the bin: t's key lies in it, and no
+          // delegate lies between its ends and the (sub-)bin's
           const bool ok = sm.out[2] != 0;
           const uint32_t sublo = lo + (sm.out[0] << fsh);
           const uint32_t subhi = hi - sublo > (1u << fsh) - 1u ? sublo + ((1u << fsh) - 1u) : hi;
-          st_coh(&ctl->tpub[0], ok ? sublo : lo);
+          const uint32_t kmax = ld_coh(&ctl->rkmax), kmin = ~ld_coh(&ctl->rknmin);
+          const bool seen = kmax >= kmin;  // always, unless the bin was empty (an internal error)
+          const uint32_t elo = ok ? sublo : lo, ehi = ok ? subhi : hi;
+          st_coh(&ctl->tpub[0], seen && kmin > elo ? kmin : elo);
           st_coh(&ctl->tpub[1], ok ? a.kD - sm.out[1] + sm.out[3] : (uint32_t)(m < 0xFFFFFFFFull ? m : 0xFFFFFFFFull));
-          st_coh(&ctl->tpub[2], ok ? subhi : hi);
+          st_coh(&ctl->tpub[2], seen && kmax < ehi ? kmax : ehi);
           st_coh(&ctl->tpub[3], ok ? sm.out[1] : ctl->cut_rank);
         }
         stamp(ctl, PH_H);
@@ -801,9 +832,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     if (m <= limit) {
       T = (uint64_t)tkey << 32;
     } else {
-      // massive ties: the exact select, from the position digits on when the
-      // bin holds a single key, stopping once t's class has one member (any
-      // T <= t with the same delegates at or above it serves Rule 2)
+      // massive ties: a radix select, from the position digits on when the
+      // bin holds a single key, stopping once t's class has at most
+      // kBoundTol members below t (any T <= t serves Rule 2, and the
+      // delegates at or above T stay within kD + slack)
       const bool one_key = tkey == bhi;
       T = tail_select(a.dkey, a.didx, (uint32_t)a.nd, one_key ? brank : a.kD, ctl->histW, &ph[PH_DSEL],
                       ctl->selpub, ctl, sm, one_key, tkey, true);
