@@ -104,6 +104,32 @@ __device__ inline void lds_sort_desc(uint64_t* buf, uint32_t P) {
   }
 }
 
+// Whole wave active.  Each lane appends the elements c with pred[c]: one
+// LDS reservation for the wave's four element slots.
+template <int CAP>
+__device__ __forceinline__ void stage_push4(Stage<CAP>& S, const bool (&pred)[4], const uint32_t (&key)[4],
+                                            const uint32_t (&idx)[4]) {
+  uint64_t m[4];
+  uint32_t pre[4], tot = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    m[c] = __ballot(pred[c]);
+    pre[c] = tot;
+    tot += (uint32_t)__popcll(m[c]);
+  }
+  if (!tot) return;
+  uint32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(&S.n, tot);
+  base = (uint32_t)__shfl((int)base, 0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (pred[c]) {
+      const uint32_t off = base + pre[c] + mbcnt(m[c]);
+      S.key[off] = key[c];
+      S.idx[off] = idx[c];
+    }
+}
+
 template <int CAP>
 __device__ __forceinline__ void stage_flush_coh(Stage<CAP>& S, uint32_t* gcount, uint32_t gcap, uint32_t* gkey,
                                                 uint32_t* gidx, Ctl* ctl, bool force, uint32_t margin) {
@@ -259,18 +285,21 @@ __device__ inline uint64_t tail_select(const uint32_t* key, const uint32_t* idx,
       const uint32_t c = claim(&ph[p], nchunks, sm);
       if (c >= nchunks) break;
       ++mine;
-#pragma unroll 2
-      for (uint32_t j = 0; j < kSelChunk; j += kTailThreads) {
-        const uint32_t i = c * kSelChunk + j + threadIdx.x;
-        if (i >= count) continue;
-        const uint32_t kk = ld_coh(&key[i]);
-        if ((kk & kmask) != kpref) continue;
-        uint64_t x = (uint64_t)kk << 32;
-        if (p >= 3) {
-          const uint32_t ip = ~ld_coh(&idx[i]);
-          if ((ip & imask) != ipref) continue;
-          x |= ip;
-        }
+      // every load of the claim first (positions only once they are digits), then the tests
+      constexpr int R = kSelChunk / kTailThreads;
+      uint32_t kv[R], iv[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t i = c * kSelChunk + (uint32_t)j * kTailThreads + threadIdx.x;
+        kv[j] = i < count ? ld_coh(&key[i]) : 0u;
+        iv[j] = i < count && p >= 3 ? ~ld_coh(&idx[i]) : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t i = c * kSelChunk + (uint32_t)j * kTailThreads + threadIdx.x;
+        if (i >= count || (kv[j] & kmask) != kpref) continue;
+        if (p >= 3 && (iv[j] & imask) != ipref) continue;
+        const uint64_t x = ((uint64_t)kv[j] << 32) | (p >= 3 ? iv[j] : 0u);
         atomicAdd(&sm.u.st.hist[(uint32_t)(x >> sh) & dm], 1u);
       }
     }
@@ -580,6 +609,48 @@ __device__ __forceinline__ void hist_add_wave(uint32_t* h, bool pred, uint32_t b
   }
 }
 
+// The four elements of every lane of a wave at once (whole wave active).
+// While all survivors of the wave fall into one bucket (sorted or tied
+// inputs, and the dense stretches of others) the wave only adds their count
+// to a pending (bucket, count) pair, wave-uniform, which goes to h[] in one
+// atomic when the bucket changes and at hist_pending_flush; otherwise one
+// atomic per survivor.  Same-address LDS atomics from every wave of a block
+// otherwise serialise.
+__device__ __forceinline__ void hist_add_wave4(uint32_t* h, const bool (&take)[4], const uint32_t (&bin)[4],
+                                               uint32_t& pbin, uint32_t& pcnt) {
+  uint64_t m[4];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    m[c] = __ballot(take[c]);
+    tot += (uint32_t)__popcll(m[c]);
+  }
+  if (!tot) return;
+  // the bucket of the first survivor (element slots in order, then lanes)
+  const int c0 = m[0] ? 0 : m[1] ? 1 : m[2] ? 2 : 3;
+  const uint32_t bc = c0 == 0 ? bin[0] : c0 == 1 ? bin[1] : c0 == 2 ? bin[2] : bin[3];
+  const uint32_t b0 = (uint32_t)__shfl((int)bc, __ffsll((unsigned long long)m[c0]) - 1);
+  bool same = true;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) same = same && (!take[c] || bin[c] == b0);
+  if (__all(same)) {
+    if (b0 != pbin) {
+      if (pcnt && lane_id() == 0) atomicAdd(&h[pbin], pcnt);
+      pbin = b0;
+      pcnt = 0;
+    }
+    pcnt += tot;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (take[c]) atomicAdd(&h[bin[c]], 1u);
+  }
+}
+__device__ __forceinline__ void hist_pending_flush(uint32_t* h, uint32_t& pbin, uint32_t& pcnt) {
+  if (pcnt && lane_id() == 0) atomicAdd(&h[pbin], pcnt);
+  pcnt = 0;
+}
+
 // Adds the block's LDS bucket counts to the global counts and clears them.
 // Block-uniform.
 __device__ __forceinline__ void hist_flush(uint32_t* h, uint32_t* g) {
@@ -604,7 +675,7 @@ __device__ inline void small_output(const TailArgs& a, uint32_t nc, TailSmem& sm
 enum { PH_H = 0, PH_Q = 1, PH_S = 2, PH_F1 = 3, PH_B1 = 4, PH_B2 = 5, PH_B3 = 6, PH_FSEL = 7, PH_FC = 13, PH_FS = 14,
        PH_DSEL = 15 };
 constexpr uint32_t kWChunk = kTailThreads * 8;
-constexpr uint32_t kSChunk = kTailThreads * 4 * 8;
+constexpr uint32_t kSChunk = kTailThreads * 4 * 16;
 constexpr uint32_t kGroup = 2048;  // output positions per sort group (a group holds < 2 kGroup)
 
 // One S-phase claim of STEPS x (kTailThreads x 4) elements of the virtual
@@ -633,19 +704,25 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
 #pragma unroll
       for (int c = 0; c < 4; ++c) vv[jj][c] = pp[jj] + c < a.n ? a.keys[pp[jj] + c] : 0u;
   }
+  uint32_t pbin = 0xFFFFFFFFu, pcnt = 0;
 #pragma unroll
   for (int jj = 0; jj < STEPS; ++jj) {
+    bool take[4];
+    uint32_t kk[4], ii[4], bin[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint64_t pos = pp[jj] + c;
-      const uint32_t kk = enc<DT>(vv[jj][c]);
-      const uint64_t cc = comp(kk, (uint32_t)pos);
-      const bool take = pos < a.n && cc >= T;
-      hist_add_wave(bh, take, take ? bm(cc) : 0u);
-      stage_push(sm.u.st.sc, take, kk, (uint32_t)pos);
+      kk[c] = enc<DT>(vv[jj][c]);
+      ii[c] = (uint32_t)pos;
+      const uint64_t cc = comp(kk[c], ii[c]);
+      take[c] = pos < a.n && cc >= T;
+      bin[c] = take[c] ? bm(cc) : 0u;
     }
+    hist_add_wave4(bh, take, bin, pbin, pcnt);
+    stage_push4(sm.u.st.sc, take, kk, ii);
     stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
   }
+  hist_pending_flush(bh, pbin, pcnt);
 }
 
 // ---- large-k sort of the fallback path ---------------------------------------
@@ -765,15 +842,22 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         const uint32_t c = claim(&ph[PH_H], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
-        for (uint32_t j = 0; j < kWChunk; j += kTailThreads) {
-          const uint64_t i = (uint64_t)c * kWChunk + j + threadIdx.x;
-          if (i < a.nd) {
-            const uint32_t kk = a.dkey[i];
-            if (kk >= lo && kk <= hi && a.didx[i] != kInvalid) {
-              atomicAdd(&sm.u.st.hist[(kk - lo) >> fsh], 1u);
-              kmx = kk > kmx ? kk : kmx;
-              knm = ~kk > knm ? ~kk : knm;
-            }
+        // every load of the claim first, then the tests
+        constexpr int R = kWChunk / kTailThreads;
+        uint32_t kv[R], iv[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const uint64_t i = (uint64_t)c * kWChunk + (uint64_t)j * kTailThreads + threadIdx.x;
+          kv[j] = i < a.nd ? a.dkey[i] : 0u;
+          iv[j] = i < a.nd ? a.didx[i] : kInvalid;
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const uint32_t kk = kv[j];
+          if (kk >= lo && kk <= hi && iv[j] != kInvalid) {
+            atomicAdd(&sm.u.st.hist[(kk - lo) >> fsh], 1u);
+            kmx = kk > kmx ? kk : kmx;
+            knm = ~kk > knm ? ~kk : knm;
           }
         }
       }
@@ -956,7 +1040,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   {
     const uint32_t nq = ld_coh(&ctl->nq) < ctl->cap_q ? ld_coh(&ctl->nq) : ctl->cap_q;
     const uint64_t total = (uint64_t)nq << a.alpha;
-    // claims of 1..8 steps of kTailThreads x 4 elements: the largest that
+    // claims of 1..16 steps of kTailThreads x 4 elements: the largest that
     // still gives every block a claim, so short re-reads spread over the device
     constexpr uint32_t kStep = kTailThreads * 4;
     uint32_t steps = kSChunk / kStep;
@@ -972,7 +1056,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       ++mine;
       if (VEC && a.alpha >= 2) {
         const uint64_t first = (uint64_t)ch * chunk;
-        if (steps == 8) s_claim_vec<DT, 8>(a, first, total, T, sm, bm, bh, ctl);
+        if (steps == 16) s_claim_vec<DT, 16>(a, first, total, T, sm, bm, bh, ctl);
+        else if (steps == 8) s_claim_vec<DT, 8>(a, first, total, T, sm, bm, bh, ctl);
         else if (steps == 4) s_claim_vec<DT, 4>(a, first, total, T, sm, bm, bh, ctl);
         else if (steps == 2) s_claim_vec<DT, 2>(a, first, total, T, sm, bm, bh, ctl);
         else s_claim_vec<DT, 1>(a, first, total, T, sm, bm, bh, ctl);
@@ -1002,14 +1087,20 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             v[c] = in[c] ? a.keys[pos[c]] : 0u;
           }
         }
+        bool take[4];
+        uint32_t kk[4], ii[4], bin[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const uint32_t kk = enc<DT>(v[c]);
-          const uint64_t cc = comp(kk, (uint32_t)pos[c]);
-          const bool take = in[c] && cc >= T;
-          hist_add_wave(bh, take, take ? bm(cc) : 0u);
-          stage_push(sm.u.st.sc, take, kk, (uint32_t)pos[c]);
+          kk[c] = enc<DT>(v[c]);
+          ii[c] = (uint32_t)pos[c];
+          const uint64_t cc = comp(kk[c], ii[c]);
+          take[c] = in[c] && cc >= T;
+          bin[c] = take[c] ? bm(cc) : 0u;
         }
+        uint32_t pbin = 0xFFFFFFFFu, pcnt = 0;
+        hist_add_wave4(bh, take, bin, pbin, pcnt);
+        hist_pending_flush(bh, pbin, pcnt);
+        stage_push4(sm.u.st.sc, take, kk, ii);
         stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * 4);
       }
     }
