@@ -324,7 +324,8 @@ constexpr int kUnroll = 8;  // 128-bit loads in flight per lane
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                               uint64_t clo, uint32_t wave, uint64_t wlen, bool fast,
-                                              uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+                                              uint32_t* dkey, uint32_t* didx, uint64_t s0, uint32_t* lh,
+                                              uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const int lw = alpha - 8;
   const uint64_t wps_mask = (1ull << lw) - 1;  // wave-loads per subrange - 1
@@ -356,7 +357,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
         if (((j + 1) & wps_mask) == 0) {
           merge_lanes<BETA>(tb, 64);
-          if (lane == 0 && sb < n) emit_delegates<BETA>(sb >> alpha, tb, dkey, didx, lh, bmax);
+          if (lane == 0 && sb < n) emit_delegates<BETA>((sb >> alpha) - s0, tb, dkey, didx, lh, bmax);
           tb.clear();
         }
       }
@@ -375,7 +376,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                 uint64_t clo, uint32_t wave, uint64_t chunk, uint32_t* dkey,
-                                                uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+                                                uint32_t* didx, uint64_t s0, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint32_t L = 1u << alpha;
   const uint32_t G = L / 64 > 8 ? L / 64 : 8;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
       }
     }
     merge_lanes<BETA>(tb, G);
-    if (l == 0) emit_delegates<BETA>(s, tb, dkey, didx, lh, bmax);
+    if (l == 0) emit_delegates<BETA>(s - s0, tb, dkey, didx, lh, bmax);
   }
 }
 
@@ -479,8 +480,31 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
   }
 }
 
+// Subranges of >= 256 elements of the chunk at clo: grouped lanes (beta >= 2,
+// full chunks) or a wave per subrange.  Delegate s goes to entries
+// (s - s0) * BETA.. of dkey / didx.
+template <int DT, int BETA, bool VEC>
+__device__ __forceinline__ void delegate_chunk_wide(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
+                                                    uint64_t clo, uint64_t chunk, bool grouped, uint32_t* dkey,
+                                                    uint32_t* didx, uint64_t s0, uint32_t* lh, uint64_t* bmax) {
+  const uint32_t wave = threadIdx.x >> 6;
+  // full chunks only: a bounds-checked copy of the unrolled grouped loop
+  // would set the register budget of the whole kernel (184 VGPRs against
+  // 60: 2 waves per SIMD instead of 8); the last chunk takes delegate_wave
+  if (grouped && clo + chunk <= n)
+    grouped_batches<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, dkey, didx, s0, lh, bmax);
+  else
+    delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk >> 2, clo + chunk <= n, dkey, didx, s0, lh, bmax);
+}
+
+constexpr uint32_t kDBuf = 512;  // delegates a block keeps in LDS until its end (occupancy: 7 waves per SIMD)
+
 // One block per chunk of `chunk` elements (a multiple of 4 * 2^alpha and of
 // 4 * 256 * kUnroll); each wave streams a contiguous quarter of the chunk.
+// With subranges of >= 256 elements and at most kDBuf delegates in the
+// chunk, the delegates collect in LDS and leave in one coalesced copy at the
+// end: stores issued between the loads would hold up each later wait for
+// loads, since one counter tracks both on this GPU.
 template <int DT, int BETA, bool VEC>
 __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                   uint64_t chunk, uint32_t* __restrict__ dkey,
@@ -490,6 +514,7 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
   __shared__ uint64_t s_bmax;
+  __shared__ uint32_t s_dk[kDBuf], s_di[kDBuf];
   for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
   if (threadIdx.x == 0) s_bmax = 0;
   __syncthreads();
@@ -499,22 +524,28 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   const uint64_t wlo = clo + wave * wlen;
   const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
   const bool grouped = BETA >= 2 && gspan && wlen % gspan == 0;
+  const uint64_t s0 = clo >> alpha;
+  const bool lds_out = alpha >= 8 && clo < n && (chunk >> alpha) * BETA <= kDBuf;  // block-uniform
   if (alpha >= 8) {
-    if (clo < n) {
-      // full chunks only: a bounds-checked copy of the unrolled grouped loop
-      // would set the register budget of the whole kernel (184 VGPRs against
-      // 60: 2 waves per SIMD instead of 8); the last chunk takes delegate_wave
-      if (grouped && clo + chunk <= n)
-        grouped_batches<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, dkey, didx, lh, &s_bmax);
-      else
-        delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, wlen, clo + chunk <= n, dkey, didx, lh, &s_bmax);
-    }
+    if (lds_out)
+      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, s_dk, s_di, s0, lh, &s_bmax);
+    else if (clo < n)
+      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, dkey, didx, 0, lh, &s_bmax);
   } else if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
     delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
   }
   __syncthreads();
+  if (lds_out) {
+    // the chunk's subranges below n: S - s0 of them in the last chunk
+    const uint64_t S = (n + (1ull << alpha) - 1) >> alpha;
+    const uint64_t ns = (chunk >> alpha) < S - s0 ? (chunk >> alpha) : S - s0;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(ns * BETA); i += 256) {
+      dkey[s0 * BETA + i] = s_dk[i];
+      didx[s0 * BETA + i] = s_di[i];
+    }
+  }
   finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax);
   if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
