@@ -365,21 +365,22 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
   }
 }
 
-// beta >= 2, subranges of 256..2048 elements: a group of G = max(8, 2^alpha/64)
-// lanes owns each subrange, so a wave works on 64/G subranges at once and
-// each lane folds about 64 of a subrange's elements before the group's
-// segmented merge (log2 G steps instead of 6).  A load instruction reads
-// 64/G segments of 16*G >= 128 contiguous bytes.  The chunk's batches of
-// 64/G subranges go to the four waves round-robin (adjacent memory, as in
-// delegate_wave); the caller checks that the chunk holds a multiple of
-// 4 * 64/G subranges.
+// beta >= 2, subranges of 256..2048 elements: a group of G = 8 lanes owns
+// each subrange, so a wave works on 8 subranges at once and each lane folds
+// 2^alpha/8 of a subrange's elements before the group's 3-step segmented
+// merge.  A load instruction reads 8 segments of 128 contiguous bytes.  (G =
+// 2^alpha/64 lanes, i.e. 32 at alpha = 11, took 30 us longer at n = 2^30;
+// 16 or 32 at alpha = 10 the same time.)  The chunk's batches of 8
+// subranges go to the four waves round-robin (adjacent memory, as in
+// delegate_wave); the caller checks that the chunk holds a multiple of 32
+// subranges.
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                 uint64_t clo, uint32_t wave, uint64_t chunk, uint32_t* dkey,
                                                 uint32_t* didx, uint64_t s0, uint32_t* lh, uint64_t* bmax) {
   const uint32_t lane = lane_id();
   const uint32_t L = 1u << alpha;
-  const uint32_t G = L / 64 > 8 ? L / 64 : 8;
+  const uint32_t G = 8;
   const uint32_t ns = 64 / G;           // subranges per batch of the wave
   const uint32_t g = lane / G, l = lane % G;
   const uint32_t lpl = L / (4 * G);     // 16-byte loads per lane per subrange (8 or 16)
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   const uint64_t wlen = chunk >> 2;
   const uint64_t clo = (uint64_t)blockIdx.x * chunk;
   const uint64_t wlo = clo + wave * wlen;
-  const uint64_t gspan = alpha >= 8 && alpha <= 11 ? (64ull / ((1u << alpha) / 64 > 8 ? (1u << alpha) / 64 : 8)) << alpha : 0;
+  const uint64_t gspan = alpha >= 8 && alpha <= 11 ? 8ull << alpha : 0;  // 64 / G subranges per wave batch
   const bool grouped = BETA >= 2 && gspan && wlen % gspan == 0;
   const uint64_t s0 = clo >> alpha;
   const bool lds_out = alpha >= 8 && clo < n && (chunk >> alpha) * BETA <= kDBuf;  // block-uniform

@@ -842,14 +842,15 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         const uint32_t c = claim(&ph[PH_H], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
-        // every load of the claim first, then the tests
+        // every load of the claim first, then the tests; padding entries have
+        // key 0, so positions are read only when the bin starts at key 0
         constexpr int R = kWChunk / kTailThreads;
         uint32_t kv[R], iv[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const uint64_t i = (uint64_t)c * kWChunk + (uint64_t)j * kTailThreads + threadIdx.x;
           kv[j] = i < a.nd ? a.dkey[i] : 0u;
-          iv[j] = i < a.nd ? a.didx[i] : kInvalid;
+          iv[j] = i >= a.nd ? kInvalid : lo == 0u ? a.didx[i] : 0u;
         }
 #pragma unroll
         for (int j = 0; j < R; ++j) {

@@ -21,7 +21,7 @@ keys of n = 2^lg_n (the sum of both times; three interleaved rounds, the
 fastest run counts); an entry is written only where a candidate beats the
 planner by more than 3%.
 
-    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single | --keep-single]
+    python -m paper_2109_08219_amd.tune [--out PATH] [--problems 512] [--reps 10] [--single | --keep-single | --keep-batched]
 """
 from __future__ import annotations
 
@@ -175,21 +175,28 @@ def main(argv=None):
     ap.add_argument("--single", action="store_true", help="also tune single problems (alpha, beta)")
     ap.add_argument("--keep-single", action="store_true",
                     help="re-tune the batched form only, keeping the single-problem entries of --out")
+    ap.add_argument("--keep-batched", action="store_true",
+                    help="re-tune single problems only, keeping the batched entries of --out")
     args = ap.parse_args(argv)
+    if args.keep_single and args.keep_batched:
+        sys.exit("--keep-single and --keep-batched exclude each other")
     kept = []
-    if args.keep_single and os.path.exists(args.out):
+    if (args.keep_single or args.keep_batched) and os.path.exists(args.out):
         with open(args.out) as f:
-            kept = [e for e in json.load(f)["entries"] if e["form"] == 0]
+            kept = [e for e in json.load(f)["entries"] if e["form"] == (1 if args.keep_batched else 0)]
     import torch
     import paper_2109_08219_amd as drt
     if not torch.cuda.is_available():
         sys.exit("the autotuner measures on the GPU; none is visible")
     t0 = time.time()
-    entries = tune_batched(drt, torch, args.problems, args.reps, log=lambda s: print(s, flush=True))
-    if args.single:
-        entries += tune_single(drt, torch, max(3, args.reps // 2), log=lambda s: print(s, flush=True))
+    if args.keep_batched:
+        entries = kept + tune_single(drt, torch, max(3, args.reps // 2), log=lambda s: print(s, flush=True))
     else:
-        entries += kept
+        entries = tune_batched(drt, torch, args.problems, args.reps, log=lambda s: print(s, flush=True))
+        if args.single:
+            entries += tune_single(drt, torch, max(3, args.reps // 2), log=lambda s: print(s, flush=True))
+        else:
+            entries += kept
     doc = {"device": torch.cuda.get_device_name(0), "problems_per_bucket": args.problems, "reps": args.reps,
            "seconds": round(time.time() - t0, 1), "entries": entries}
     with open(args.out, "w") as f:
