@@ -383,7 +383,7 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
   const uint32_t G = 8;
   const uint32_t ns = 64 / G;           // subranges per batch of the wave
   const uint32_t g = lane / G, l = lane % G;
-  const uint32_t lpl = L / (4 * G);     // 16-byte loads per lane per subrange (8 or 16)
+  const uint32_t lpl = L / (4 * G);     // 16-byte loads per lane per subrange (2^alpha / 32: 8..64)
   const uint64_t nbatch = (chunk >> alpha) / ns;
   for (uint64_t bi = wave; bi < nbatch; bi += 4) {
     const uint64_t s = (clo >> alpha) + bi * ns + g;
