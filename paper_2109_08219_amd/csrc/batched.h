@@ -35,6 +35,7 @@ constexpr uint64_t kBMaxN = 1ull << 22;   // largest n handled in a workgroup
 constexpr int kBU = 8;                    // 1 KiB wave loads in flight per wave step
 constexpr uint32_t kBStep = 256 * kBU;    // keys per wave step
 constexpr int kBufWord3 = 0x00020000;     // buffer resource word 3 for gfx9-family raw buffers
+constexpr uint64_t kBSplitMinN = 1u << 16;  // problems above this may keep their delegate vector in global memory
 constexpr uint32_t kBTileLog = 18;        // a split problem's delegate vector is built in tiles of
                                           // 2^max(kBTileLog, alpha) keys, one workgroup each (fewer where a
                                           // tile's delegates would not fit its LDS: at most 4096 entries)

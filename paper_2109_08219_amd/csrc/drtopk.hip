@@ -481,7 +481,7 @@ int batched_alpha(uint64_t n, uint32_t k, int* beta) {
   const uint64_t bt = b == 2 ? 2 : 1;
   auto entries = [n, bt](int a) { return ((n + (1ull << a) - 1) >> a) * bt; };
   int r = 0;
-  if (n > (1ull << kBTileLog)) {
+  if (n > kBSplitMinN) {
     // split across workgroups: the delegate vector lives in global memory, so
     // it may hold up to kBMaxSG entries and Rule 4's shorter subranges apply
     // (at least 16 keys; tiles shrink so a tile's delegates fit its
@@ -531,10 +531,12 @@ BatchDesc make_desc(const drtopk_problem_t& q) {
 }
 
 // Tiles of a problem's delegate vector (one workgroup each): problems of
-// more than 2^kBTileLog keys on the delegate route are split so several
-// workgroups stream them (their subranges hold at least 16 keys).
+// more than kBSplitMinN keys on the delegate route are split so several
+// workgroups stream them (their subranges hold at least 16 keys); one whose
+// delegate vector exceeds the LDS (4096 entries) always spans two tiles or
+// more, since a tile holds at most 4096 delegates.
 uint32_t batched_tiles(const BatchDesc& d) {
-  if (d.n <= (1ull << kBTileLog) || d.n <= kBSmallN || d.alpha < 4) return 1;
+  if (d.n <= kBSplitMinN || d.n <= kBSmallN || d.alpha < 4) return 1;
   const uint32_t tlog = tile_log(d.alpha, d.beta);
   return (uint32_t)((d.n + (1ull << tlog) - 1) >> tlog);
 }

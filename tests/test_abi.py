@@ -203,10 +203,10 @@ def test_batched_routes_without_gpu():
                     assert (r, a) == (3, 0), (n, k, r, a)
                     continue
                 S = -(-n // (1 << a))
-                # one workgroup's LDS holds the delegate vector; problems split across
-                # workgroups (n > 2^18) keep it in global memory, up to 32768 entries,
-                # with subranges of at least 16 keys
-                if n > (1 << 18):
+                # one workgroup's LDS holds the delegate vector; problems that may be split
+                # across workgroups (n > 2^16) keep it in global memory, up to 32768
+                # entries, with subranges of at least 16 keys
+                if n > (1 << 16):
                     assert r == 2 and 4 <= a <= 24 and k < S <= 32768, (n, k, r, a)
                 else:
                     assert r == 2 and 2 <= a <= 24 and k < S <= 4096, (n, k, r, a)

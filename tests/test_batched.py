@@ -72,8 +72,10 @@ def test_routes_are_planned():
     r, a = drt.batched_route(1 << 20, 1024)
     # split across workgroups: the delegate vector in global memory, up to 32768 entries
     assert r == 2 and a >= 4 and -(-(1 << 20) // (1 << a)) <= 32768
-    r, a = drt.batched_route(1 << 18, 1024)  # one workgroup: the vector in its LDS
-    assert r == 2 and -(-(1 << 18) // (1 << a)) <= 4096
+    r, a = drt.batched_route(1 << 18, 1024)  # above 2^16 keys the vector may live in global memory too
+    assert r == 2 and a >= 4 and -(-(1 << 18) // (1 << a)) <= 32768
+    r, a = drt.batched_route(1 << 16, 1024)  # one workgroup: the vector in its LDS
+    assert r == 2 and -(-(1 << 16) // (1 << a)) <= 4096
     assert drt.batched_route((1 << 22) + 1, 10)[0] == 0
     assert drt.batched_route(1 << 16, 2049)[0] == 0
 
@@ -247,14 +249,15 @@ def test_beta2_workload_exact():
 
 @pytest.mark.parametrize("beta", [1, 2])
 def test_split_problems(beta):
-    """Problems above 2^18 keys on the delegate route: several workgroups build
+    """Problems above 2^16 keys on the delegate route: several workgroups build
     the delegate vector, the last to arrive finishes.  Ragged tails, unaligned
     views, k-only outputs, adversarial inputs (survivor overflow after the
     split) and repeated launches (the arrival counters restart at zero)."""
     drt.tune_set(beta2_table() if beta == 2 else [])
     hosts = []
     for i, (n, k) in enumerate([((1 << 18) + 1, 1), ((1 << 18) + 3, 7), ((1 << 19) + 2, 500), ((1 << 20) + 7, 2048),
-                                ((1 << 22) - 1, 1000), (1 << 22, 1), (3 << 19, 64)]):
+                                ((1 << 22) - 1, 1000), (1 << 22, 1), (3 << 19, 64), ((1 << 16) + 5, 2048),
+                                ((1 << 17) + 3, 1500), (3 << 16, 900)]):
         for kind in ("uniform_u32", "normal_f32"):
             x, dt = synth.keys(kind, n, 800 + 2 * i + (kind == "normal_f32"))
             assert drt.batched_plan(n, k)[::2] == (2, beta)
