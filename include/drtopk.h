@@ -131,8 +131,8 @@ typedef struct {
  * method of Sections 4-5 inside the workgroup's LDS); larger ones run one
  * after another through the single-problem path, on the same stream.  Any
  * invalid descriptor, or count >= 2^24, fails the whole call with
- * DRTOPK_EINVAL before any work is enqueued.  Problems of more than 2^18 keys
- * on the delegate route have their delegate vector built by several
+ * DRTOPK_EINVAL before any work is enqueued.  Problems of more than 2^16 keys
+ * on the delegate route may have their delegate vector built by several
  * workgroups.  Output buffers of different problems must not overlap. */
 int topk_select_batched(const drtopk_problem_t* problems, uint32_t count, void* stream);
 
