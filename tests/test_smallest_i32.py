@@ -91,7 +91,32 @@ def _mixed_problems(count, seed):
     return hosts
 
 
-def test_batched_mixed_codecs_and_orders():
+def beta2_table():
+    """Rule 4's alpha with two delegates per subrange in every bucket of the batched form."""
+    drt.tune_set([])
+    entries = []
+    for lg_n in range(12, 23):
+        for lg_k in range(0, 12):
+            n, k = max(1 << lg_n, 4097), 1 << lg_k
+            if k <= n:
+                r, a, _ = drt.batched_plan(n, k)
+                if r == 2:
+                    entries.append((drt.FORM_BATCHED, lg_n, lg_k, a, 2))
+    return entries
+
+
+@pytest.mark.parametrize("beta", [1, 2])
+def test_batched_mixed_codecs_and_orders(beta):
+    saved = drt.tune_get()
+    try:
+        if beta == 2:
+            drt.tune_set(beta2_table())
+        batched_mixed(beta)
+    finally:
+        drt.tune_set(saved)
+
+
+def batched_mixed(beta):
     hosts = _mixed_problems(300, 611)
     # split problems (several workgroups per delegate vector) in both orders
     for j, kind in enumerate(("normal_f32", "uniform_i32")):
@@ -99,7 +124,9 @@ def test_batched_mixed_codecs_and_orders():
         hosts.append((x, dt, 2048, j == 1))
         hosts.append((x, dt, 1000, j == 0))
     tensors = [(dev(x), k, None, largest) for x, dt, k, largest in hosts]
-    say("batched mixed", len(hosts))
+    if beta == 2:
+        assert sum(drt.batched_plan(x.shape[0], k)[2] == 2 for x, _, k, _ in hosts) > len(hosts) // 2
+    say("batched mixed", len(hosts), "beta", beta)
     b = drt.Batch(tensors)
     b.run()
     torch.cuda.synchronize()
