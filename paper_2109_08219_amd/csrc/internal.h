@@ -86,6 +86,7 @@ struct Ctl {
   uint32_t rknmin;    // refinement: complement of the smallest delegate key in the cut bin
   uint64_t tstamp[kPhases + 2];  // device real-time clock: tail start, each phase's completion
   uint64_t max1;  // largest delegate composite = largest element (the k = 1 answer)
+  uint32_t dknmin;  // complement of the smallest delegate key (0 = no delegate)
   // bucket select (tail variant 3), [0] over the delegates, [1] over the survivors
   uint64_t bmax[2];   // largest composite of the source
   uint64_t bnmin[2];  // complement of the smallest

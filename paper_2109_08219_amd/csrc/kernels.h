@@ -224,9 +224,16 @@ __device__ __forceinline__ void stage_flush(Stage<CAP>& S, uint32_t* gcount, uin
 // ---------------------------------------------------------------------------
 // delegate vector
 
+// Per-thread summary of the delegates this thread emitted: the largest
+// composite, and the complement of the smallest key (0 = none).
+struct DelAcc {
+  uint64_t mx = 0;
+  uint32_t nmn = 0;
+};
+
 template <int BETA>
 __device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb, uint32_t* dkey,
-                                               uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+                                               uint32_t* didx, uint32_t* lh, DelAcc& acc) {
 #pragma unroll
   for (int j = 0; j < BETA; ++j) {
     const uint32_t kk = comp_key(tb.c[j]);
@@ -234,8 +241,9 @@ __device__ __forceinline__ void emit_delegates(uint64_t s, const TopB<BETA>& tb,
     didx[s * BETA + j] = comp_pos(tb.c[j]);  // padding (composite 0) gives 0xFFFFFFFF
     atomicAdd(&lh[top_bin(kk)], 1u);
     atomicAdd(&lh[kBins + log_bin(kk)], 1u);
+    if (tb.c[j]) acc.nmn = ~kk > acc.nmn ? ~kk : acc.nmn;
   }
-  atomicMax((unsigned long long*)bmax, (unsigned long long)tb.c[0]);
+  acc.mx = tb.c[0] > acc.mx ? tb.c[0] : acc.mx;
 }
 
 template <int DT>
@@ -260,15 +268,38 @@ struct DirectOut {
 // the bin holding the kD-th largest delegate, and keeps the map whose cut
 // leaves the smaller set W (all delegates in that bin or above).
 __device__ inline void finish_delegates(const uint32_t* lh, Ctl* ctl, uint32_t kD, uint32_t* s_scan,
-                                        uint32_t* s_out, int* s_last, const uint64_t* bmax) {
+                                        uint32_t* s_out, int* s_last, DelAcc acc, uint64_t* s_red) {
   for (int i = threadIdx.x; i < kBins; i += blockDim.x) {
     const uint32_t a = lh[i], b = lh[kBins + i];
     if (a) atomicAdd(&ctl->histD[0][i], a);
     if (b) atomicAdd(&ctl->histL[i], b);
   }
-  // the largest delegate is the largest element: the k = 1 answer, and the top
-  // of the survivors' bucket map in the tail
-  if (threadIdx.x == 0 && *bmax) atomicMax((unsigned long long*)&ctl->max1, (unsigned long long)*bmax);
+  // the block's largest delegate and smallest delegate key, over its waves
+  // (s_red: 2 entries per wave)
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t m = shfl_xor64(acc.mx, o);
+    const uint32_t q = (uint32_t)__shfl_xor((int)acc.nmn, o);
+    acc.mx = m > acc.mx ? m : acc.mx;
+    acc.nmn = q > acc.nmn ? q : acc.nmn;
+  }
+  const uint32_t nw = blockDim.x >> 6;
+  if (lane_id() == 0) {
+    s_red[threadIdx.x >> 6] = acc.mx;
+    s_red[nw + (threadIdx.x >> 6)] = acc.nmn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < nw; ++w) {
+      acc.mx = s_red[w] > acc.mx ? s_red[w] : acc.mx;
+      acc.nmn = (uint32_t)s_red[nw + w] > acc.nmn ? (uint32_t)s_red[nw + w] : acc.nmn;
+    }
+    // the largest delegate is the largest element: the k = 1 answer, and the
+    // top of the survivors' bucket map in the tail; the smallest delegate key
+    // lets the tail clip the cut bin to the keys present
+    if (acc.mx) atomicMax((unsigned long long*)&ctl->max1, (unsigned long long)acc.mx);
+    if (acc.nmn) atomicMax(&ctl->dknmin, acc.nmn);
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) *s_last = (atomicAdd(&ctl->ticketD[0], 1u) == gridDim.x - 1) ? 1 : 0;
@@ -325,7 +356,7 @@ template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                               uint64_t clo, uint32_t wave, uint64_t wlen, bool fast,
                                               uint32_t* dkey, uint32_t* didx, uint64_t s0, uint32_t* lh,
-                                              uint64_t* bmax) {
+                                              DelAcc& acc) {
   const uint32_t lane = lane_id();
   const int lw = alpha - 8;
   const uint64_t wps_mask = (1ull << lw) - 1;  // wave-loads per subrange - 1
@@ -357,7 +388,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
         if (((j + 1) & wps_mask) == 0) {
           merge_lanes<BETA>(tb, 64);
-          if (lane == 0 && sb < n) emit_delegates<BETA>((sb >> alpha) - s0, tb, dkey, didx, lh, bmax);
+          if (lane == 0 && sb < n) emit_delegates<BETA>((sb >> alpha) - s0, tb, dkey, didx, lh, acc);
           tb.clear();
         }
       }
@@ -377,7 +408,7 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                 uint64_t clo, uint32_t wave, uint64_t chunk, uint32_t* dkey,
-                                                uint32_t* didx, uint64_t s0, uint32_t* lh, uint64_t* bmax) {
+                                                uint32_t* didx, uint64_t s0, uint32_t* lh, DelAcc& acc) {
   const uint32_t lane = lane_id();
   const uint32_t L = 1u << alpha;
   const uint32_t G = 8;
@@ -437,7 +468,7 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
       }
     }
     merge_lanes<BETA>(tb, G);
-    if (l == 0) emit_delegates<BETA>(s - s0, tb, dkey, didx, lh, bmax);
+    if (l == 0) emit_delegates<BETA>(s - s0, tb, dkey, didx, lh, acc);
   }
 }
 
@@ -447,7 +478,7 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                uint64_t wlo, uint64_t whi, bool fast,
-                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh, uint64_t* bmax) {
+                                               uint32_t* dkey, uint32_t* didx, uint32_t* lh, DelAcc& acc) {
   const uint32_t lane = lane_id();
   const uint32_t gl = 1u << (alpha - 2);  // lanes per subrange
   const uint64_t nwl = (whi + 255 - wlo) >> 8;
@@ -475,7 +506,7 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
         for (int c = 0; c < 4; ++c)
           if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
         merge_lanes<BETA>(tb, gl);
-        if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh, bmax);
+        if ((lane & (gl - 1)) == 0 && p < n) emit_delegates<BETA>(p >> alpha, tb, dkey, didx, lh, acc);
       }
     }
   }
@@ -487,15 +518,15 @@ __device__ __forceinline__ void delegate_group(const uint32_t* __restrict__ keys
 template <int DT, int BETA, bool VEC>
 __device__ __forceinline__ void delegate_chunk_wide(const uint32_t* __restrict__ keys, uint64_t n, int alpha,
                                                     uint64_t clo, uint64_t chunk, bool grouped, uint32_t* dkey,
-                                                    uint32_t* didx, uint64_t s0, uint32_t* lh, uint64_t* bmax) {
+                                                    uint32_t* didx, uint64_t s0, uint32_t* lh, DelAcc& acc) {
   const uint32_t wave = threadIdx.x >> 6;
   // full chunks only: a bounds-checked copy of the unrolled grouped loop
   // would set the register budget of the whole kernel (184 VGPRs against
   // 60: 2 waves per SIMD instead of 8); the last chunk takes delegate_wave
   if (grouped && clo + chunk <= n)
-    grouped_batches<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, dkey, didx, s0, lh, bmax);
+    grouped_batches<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk, dkey, didx, s0, lh, acc);
   else
-    delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk >> 2, clo + chunk <= n, dkey, didx, s0, lh, bmax);
+    delegate_wave<DT, BETA, VEC>(keys, n, alpha, clo, wave, chunk >> 2, clo + chunk <= n, dkey, didx, s0, lh, acc);
 }
 
 constexpr uint32_t kDBuf = 512;  // delegates a block keeps in LDS until its end (occupancy: 7 waves per SIMD)
@@ -514,11 +545,11 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
-  __shared__ uint64_t s_bmax;
+  __shared__ uint64_t s_red[8];
   __shared__ uint32_t s_dk[kDBuf], s_di[kDBuf];
   for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
-  if (threadIdx.x == 0) s_bmax = 0;
   __syncthreads();
+  DelAcc acc;
   const uint32_t wave = threadIdx.x >> 6;
   const uint64_t wlen = chunk >> 2;
   const uint64_t clo = (uint64_t)blockIdx.x * chunk;
@@ -529,13 +560,13 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
   const bool lds_out = alpha >= 8 && clo < n && (chunk >> alpha) * BETA <= kDBuf;  // block-uniform
   if (alpha >= 8) {
     if (lds_out)
-      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, s_dk, s_di, s0, lh, &s_bmax);
+      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, s_dk, s_di, s0, lh, acc);
     else if (clo < n)
-      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, dkey, didx, 0, lh, &s_bmax);
+      delegate_chunk_wide<DT, BETA, VEC>(keys, n, alpha, clo, chunk, grouped, dkey, didx, 0, lh, acc);
   } else if (wlo < n) {
     const uint64_t whi = wlo + wlen < n ? wlo + wlen : n;
     const bool fast = (wlo + wlen <= n);
-    delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, &s_bmax);
+    delegate_group<DT, BETA, VEC>(keys, n, alpha, wlo, whi, fast, dkey, didx, lh, acc);
   }
   __syncthreads();
   if (lds_out) {
@@ -547,7 +578,7 @@ __global__ __launch_bounds__(256) void k_delegate(const uint32_t* __restrict__ k
       didx[s0 * BETA + i] = s_di[i];
     }
   }
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, acc, s_red);
   if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 
@@ -562,20 +593,20 @@ __global__ __launch_bounds__(256) void k_delegate_thread(const uint32_t* __restr
   __shared__ uint32_t s_scan[256];
   __shared__ uint32_t s_out[4];
   __shared__ int s_last;
-  __shared__ uint64_t s_bmax;
+  __shared__ uint64_t s_red[8];
   for (int i = threadIdx.x; i < 2 * kBins; i += 256) lh[i] = 0;
-  if (threadIdx.x == 0) s_bmax = 0;
   __syncthreads();
+  DelAcc acc;
   for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < S; s += (uint64_t)gridDim.x * 256) {
     TopB<BETA> tb;
     tb.clear();
     const uint64_t lo = s << alpha;
     const uint64_t hi = (lo + (1ull << alpha)) < n ? lo + (1ull << alpha) : n;
     for (uint64_t p = lo; p < hi; ++p) tb.push(comp(enc<DT>(keys[p]), (uint32_t)p));
-    emit_delegates<BETA>(s, tb, dkey, didx, lh, &s_bmax);
+    emit_delegates<BETA>(s, tb, dkey, didx, lh, acc);
   }
   __syncthreads();
-  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, &s_bmax);
+  finish_delegates(lh, ctl, k, s_scan, s_out, &s_last, acc, s_red);
   if (out.on && s_last && threadIdx.x == 0) write_out<DT>(ld_coh64(&ctl->max1), 0, 1, out.vals, out.idx, out.kth);
 }
 

@@ -824,7 +824,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   // found by a radix select over the delegates.
   uint64_t T = 0;
   if (!a.all) {
-    const uint32_t lo = ctl->cut_lo, hi = ctl->cut_hi;
+    // the cut bin's key interval, clipped to the delegate keys present (t's
+    // key lies in both; no delegate lies between their ends)
+    uint32_t lo = ctl->cut_lo, hi = ctl->cut_hi;
+    {
+      const uint32_t dmax = comp_key(ctl->max1), dmin = ~ctl->dknmin;
+      const uint32_t clo = lo > dmin ? lo : dmin, chi = hi < dmax ? hi : dmax;
+      if (ctl->dknmin && clo <= chi) {
+        lo = clo;
+        hi = chi;
+      }
+    }
     const uint32_t crowd = (1u << 22) >> (a.alpha < 22 ? a.alpha : 22);
     const uint64_t limit = (uint64_t)a.kD + a.slack;
     uint64_t m = (uint64_t)a.kD - ctl->cut_rank + ctl->cut_count;
