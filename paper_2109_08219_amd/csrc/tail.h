@@ -845,7 +845,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     if (refine) {
       const uint32_t fsh = bitlen32(hi - lo) > 11u ? bitlen32(hi - lo) - 11u : 0u;
       for (int i = threadIdx.x; i < kBins; i += kTailThreads) sm.u.st.hist[i] = 0;
-      const uint32_t nchunks = (uint32_t)((a.nd + kWChunk - 1) / kWChunk);
+      // claims of 16 delegates per thread: 2^21 delegates take one round of
+      // claims over the device
+      constexpr uint32_t kHChunk = kTailThreads * 16;
+      const uint32_t nchunks = (uint32_t)((a.nd + kHChunk - 1) / kHChunk);
       uint32_t mine = 0;
       uint32_t kmx = 0, knm = 0;  // largest key in the bin, complement of the smallest
       for (;;) {
@@ -854,11 +857,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         ++mine;
         // every load of the claim first, then the tests; padding entries have
         // key 0, so positions are read only when the bin starts at key 0
-        constexpr int R = kWChunk / kTailThreads;
+        constexpr int R = kHChunk / kTailThreads;
         uint32_t kv[R], iv[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const uint64_t i = (uint64_t)c * kWChunk + (uint64_t)j * kTailThreads + threadIdx.x;
+          const uint64_t i = (uint64_t)c * kHChunk + (uint64_t)j * kTailThreads + threadIdx.x;
           kv[j] = i < a.nd ? a.dkey[i] : 0u;
           iv[j] = i >= a.nd ? kInvalid : lo == 0u ? a.didx[i] : 0u;
         }
