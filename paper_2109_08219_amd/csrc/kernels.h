@@ -42,6 +42,20 @@ struct TopB {
       c[0] = g[0] ? x : c[0];
     }
   }
+  // Four elements at once (BETA >= 4): a 5-comparator network sorts them,
+  // the larger of c[BETA-1-j] and the j-th largest of the four replaces
+  // c[BETA-1-j] (the top BETA of both lists, as a bitonic sequence), and
+  // half-cleaners sort the list again: 21 compare-exchanges or maxima at
+  // BETA = 8 where four single insertions take 32.
+  __device__ __forceinline__ void push4(uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3) {
+    static_assert(BETA >= 4, "push4 needs a list of at least four");
+    cx(x0, x1); cx(x2, x3); cx(x0, x2); cx(x1, x3); cx(x1, x2);
+    c[BETA - 1] = c[BETA - 1] > x0 ? c[BETA - 1] : x0;
+    c[BETA - 2] = c[BETA - 2] > x1 ? c[BETA - 2] : x1;
+    c[BETA - 3] = c[BETA - 3] > x2 ? c[BETA - 3] : x2;
+    c[BETA - 4] = c[BETA - 4] > x3 ? c[BETA - 4] : x3;
+    clean();
+  }
   // Replace this list by the top-BETA of (this list, the list of a lane in
   // the other M-half of this lane's 2M-block); after the step both lanes hold
   // the same list, so steps M = 1, 2, 4, ... leave every lane of each block
@@ -54,16 +68,23 @@ struct TopB {
     for (int j = 0; j < BETA; ++j) o[j] = lane_cross64<M>(c[j]);
 #pragma unroll
     for (int j = 0; j < BETA; ++j) c[j] = c[j] > o[BETA - 1 - j] ? c[j] : o[BETA - 1 - j];
+    clean();
+  }
+
+ private:
+  // a >= b afterwards
+  static __device__ __forceinline__ void cx(uint64_t& a, uint64_t& b) {
+    const uint64_t x = a, y = b;
+    a = x > y ? x : y;
+    b = x > y ? y : x;
+  }
+  // a bitonic list sorted descending
+  __device__ __forceinline__ void clean() {
 #pragma unroll
     for (int s = BETA / 2; s >= 1; s >>= 1) {
 #pragma unroll
-      for (int j = 0; j < BETA; ++j) {
-        if ((j & s) == 0) {
-          uint64_t a = c[j], b = c[j + s];
-          c[j] = a > b ? a : b;
-          c[j + s] = a > b ? b : a;
-        }
-      }
+      for (int j = 0; j < BETA; ++j)
+        if ((j & s) == 0) cx(c[j], c[j + s]);
     }
   }
 };
@@ -383,9 +404,16 @@ __device__ __forceinline__ void delegate_wave(const uint32_t* __restrict__ keys,
       if (j < nwl) {
         const uint64_t sb = first + ((j >> lw) << (alpha + 2));
         const uint64_t p = sb + ((j & wps_mask) << 8) + lane * 4;
+        if constexpr (BETA >= 4) {
+          uint64_t x[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
+          for (int c = 0; c < 4; ++c) x[c] = (fast || p + c < n) ? comp(enc<DT>(v[u][c]), (uint32_t)(p + c)) : 0ull;
+          tb.push4(x[0], x[1], x[2], x[3]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (fast || p + c < n) tb.push(comp(enc<DT>(v[u][c]), (uint32_t)(p + c)));
+        }
         if (((j + 1) & wps_mask) == 0) {
           merge_lanes<BETA>(tb, 64);
           if (lane == 0 && sb < n) emit_delegates<BETA>((sb >> alpha) - s0, tb, dkey, didx, lh, acc);
@@ -462,8 +490,13 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t pu = (uint32_t)p0 + (uint32_t)u * G * 4;
+          if constexpr (BETA >= 4) {
+            tb.push4(comp(enc<DT>(v[u][0]), pu), comp(enc<DT>(v[u][1]), pu + 1), comp(enc<DT>(v[u][2]), pu + 2),
+                     comp(enc<DT>(v[u][3]), pu + 3));
+          } else {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) tb.push(comp(enc<DT>(v[u][c]), pu + c));
+            for (int c = 0; c < 4; ++c) tb.push(comp(enc<DT>(v[u][c]), pu + c));
+          }
         }
       }
     }
