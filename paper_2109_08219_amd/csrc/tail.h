@@ -959,16 +959,18 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   // delegates than k: every subrange with beta real delegates is re-read.)
   if (threadIdx.x == 0) { sm.u.st.sq.n = 0; sm.u.st.sc.n = 0; }
   {
-    constexpr uint32_t kQChunk = kTailThreads * 8;
+    // subranges per thread and claim: 8 at beta <= 2, else 16 / beta (the
+    // stages then hold a whole claim's output either way)
+    constexpr uint32_t kQR = BETA <= 2 ? 8 : 16 / BETA;
+    constexpr uint32_t kQChunk = kTailThreads * kQR;
     const uint32_t nchunks = (uint32_t)((a.S + kQChunk - 1) / kQChunk);
     uint32_t mine = 0;
-    uint32_t c = 0, sub = 8;
     if constexpr (BETA <= 2) {
       // every delegate of the claim's 8 x kTailThreads subranges is loaded
       // before any is tested (16 loads in flight per thread)
       using DV = typename std::conditional<BETA == 1, uint32_t, u32x2>::type;
       for (;;) {
-        c = claim(&ph[PH_Q], nchunks, sm);
+        const uint32_t c = claim(&ph[PH_Q], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
         DV dk[8], di[8];
@@ -1004,38 +1006,44 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         stage_flush2_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, 8 * kTailThreads, sm.u.st.sc, &ctl->nc,
                          ctl->cap_c, a.ckey, a.cidx, 8 * kTailThreads * BETA, ctl);
       }
-      sub = 0;
-    }
-    for (;;) {
-      if constexpr (BETA <= 2) break;
-      if (sub == 8) {
-        c = claim(&ph[PH_Q], nchunks, sm);
+    } else {
+      // beta = 4 or 8: each subrange's delegate list is beta / 4 16-byte
+      // vectors of keys and as many of positions, all of the claim's loaded
+      // before any is tested
+      constexpr int NV = BETA / 4;
+      for (;;) {
+        const uint32_t c = claim(&ph[PH_Q], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
-        sub = 0;
-      }
-      const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)(sub++) * kTailThreads + threadIdx.x;
-      const bool ok = s < a.S;
-      bool scan = false;
-      if (ok) {
-        const uint64_t ds = s * BETA + BETA - 1;
-        scan = comp(a.dkey[ds], a.didx[ds]) > T && a.didx[ds] != kInvalid;
-      }
-      stage_push(sm.u.st.sq, scan, (uint32_t)s, 0u);
+        u32x4 dk[kQR][NV], di[kQR][NV];
 #pragma unroll
-      for (int j = 0; j < BETA; ++j) {
-        bool take = false;
-        uint32_t kk = 0, ii = 0;
-        if (ok && !scan) {
-          kk = a.dkey[s * BETA + j];
-          ii = a.didx[s * BETA + j];
-          take = ii != kInvalid && comp(kk, ii) >= T;
+        for (int i = 0; i < (int)kQR; ++i) {
+          const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)i * kTailThreads + threadIdx.x;
+          const uint64_t sc = s < a.S ? s : 0;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            dk[i][v] = reinterpret_cast<const u32x4*>(a.dkey)[sc * NV + v];
+            di[i][v] = reinterpret_cast<const u32x4*>(a.didx)[sc * NV + v];
+          }
         }
-        hist_add_wave(bh, take, take ? bm(comp(kk, ii)) : 0u);
-        stage_push(sm.u.st.sc, take, kk, ii);
+#pragma unroll
+        for (int i = 0; i < (int)kQR; ++i) {
+          const uint64_t s = (uint64_t)c * kQChunk + (uint64_t)i * kTailThreads + threadIdx.x;
+          const bool ok = s < a.S;
+          const uint32_t kl = dk[i][NV - 1][3], il = di[i][NV - 1][3];  // the beta-th delegate
+          const bool scan = ok && il != kInvalid && comp(kl, il) > T;
+          stage_push(sm.u.st.sq, scan, (uint32_t)s, 0u);
+#pragma unroll
+          for (int j = 0; j < BETA; ++j) {
+            const uint32_t kk = dk[i][j >> 2][j & 3], ii = di[i][j >> 2][j & 3];
+            const bool take = ok && !scan && ii != kInvalid && comp(kk, ii) >= T;
+            hist_add_wave(bh, take, take ? bm(comp(kk, ii)) : 0u);
+            stage_push(sm.u.st.sc, take, kk, ii);
+          }
+        }
+        stage_flush2_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, kQR * kTailThreads, sm.u.st.sc, &ctl->nc,
+                         ctl->cap_c, a.ckey, a.cidx, kQR * kTailThreads * BETA, ctl);
       }
-      stage_flush_coh(sm.u.st.sq, &ctl->nq, ctl->cap_q, a.Q, nullptr, ctl, false, kTailThreads);
-      stage_flush_coh(sm.u.st.sc, &ctl->nc, ctl->cap_c, a.ckey, a.cidx, ctl, false, kTailThreads * BETA);
     }
     // everything a block staged is published before it reports its chunks:
     // a phase's completion then implies all of its output is visible
