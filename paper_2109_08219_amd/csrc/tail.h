@@ -725,6 +725,62 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
   hist_pending_flush(bh, pbin, pcnt);
 }
 
+// One B2 claim: the survivors [first, first + R x kTailThreads) (below nc)
+// all loaded first, then scattered in batches of 8 per thread: bucket
+// counts and each element's rank in its bucket from an LDS histogram, one
+// global reservation per nonzero bucket up to b*, then the stores.
+template <int R>
+__device__ __forceinline__ void b2_claim(const TailArgs& a, uint32_t first, uint32_t nc, uint32_t bstar,
+                                         const BucketMap& bm, TailSmem& sm, Ctl* ctl) {
+  constexpr int kPer = 8;
+  constexpr int PER = kBins / kTailThreads;
+  uint32_t* lh = sm.u.st.hist;
+  uint32_t kk[R], ii[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const uint32_t i = first + j * kTailThreads + threadIdx.x;
+    kk[j] = i < nc ? ld_coh(&a.ckey[i]) : 0u;
+    ii[j] = i < nc ? ld_coh(&a.cidx[i]) : 0u;
+  }
+#pragma unroll
+  for (int b0 = 0; b0 < R; b0 += kPer) {
+    for (int i = threadIdx.x; i < kBins; i += kTailThreads) lh[i] = 0;
+    __syncthreads();  // histogram cleared
+    uint32_t bb[kPer], rk[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t i = first + (b0 + j) * kTailThreads + threadIdx.x;
+      bb[j] = i < nc ? bm(comp(kk[b0 + j], ii[b0 + j])) : (uint32_t)kBins;
+      rk[j] = bb[j] <= bstar ? atomicAdd(&lh[bb[j]], 1u) : 0u;
+    }
+    __syncthreads();
+    uint32_t base[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {  // reserve each bucket's range for this batch
+      const uint32_t b = threadIdx.x * PER + j;
+      const uint32_t cnt = lh[b];
+      base[j] = cnt ? ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], cnt) : 0u;
+    }
+    __syncthreads();  // every count read before it is overwritten by the base
+#pragma unroll
+    for (int j = 0; j < PER; ++j) lh[threadIdx.x * PER + j] = base[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      if (bb[j] <= bstar) {
+        const uint32_t slot = lh[bb[j]] + rk[j];
+        if (slot < a.cap_s) {
+          st_coh(&a.skey[slot], kk[b0 + j]);
+          st_coh(&a.sidx[slot], ii[b0 + j]);
+        } else {
+          flag_err(ctl, ERR_CAP);
+        }
+      }
+    }
+    __syncthreads();  // the bases are read before the next batch clears them
+  }
+}
+
 // ---- large-k sort of the fallback path ---------------------------------------
 // The k compacted entries (okey / oidx) sorted without leaving the kernel:
 // tiles of kSortTile sorted in LDS into A, then runs merged pairwise, one
@@ -1238,58 +1294,21 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     // B2: scatter the buckets up to b* into bucket order
     {
       const uint32_t bstar = ld_coh(&ctl->bstar);
-      const uint32_t nchunks = (nc + kWChunk - 1) / kWChunk;
+      // claims of R x kTailThreads survivors, R = 8, 16 or 32: the largest
+      // that still gives every block a claim, so that many survivors (sorted
+      // or tied inputs) take fewer claims, each with all of its loads in flight
+      uint32_t R = 32;
+      while (R > 8 && (nc + R * kTailThreads - 1) / (R * kTailThreads) < gridDim.x) R >>= 1;
+      const uint32_t chunk = R * kTailThreads;
+      const uint32_t nchunks = (nc + chunk - 1) / chunk;
       uint32_t mine = 0;
-      // per claim: every load first; bucket counts and each element's rank in
-      // its bucket from an LDS histogram; one global reservation per nonzero
-      // bucket; then the stores
-      constexpr int kPer = kWChunk / kTailThreads;
-      constexpr int PER = kBins / kTailThreads;
-      uint32_t* lh = sm.u.st.hist;
       for (;;) {
         const uint32_t c = claim(&ph[PH_B2], nchunks, sm);
         if (c >= nchunks) break;
         ++mine;
-        for (int i = threadIdx.x; i < kBins; i += kTailThreads) lh[i] = 0;
-        uint32_t kk[kPer], ii[kPer], bb[kPer], rk[kPer];
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
-          kk[j] = i < nc ? ld_coh(&a.ckey[i]) : 0u;
-          ii[j] = i < nc ? ld_coh(&a.cidx[i]) : 0u;
-        }
-        __syncthreads();  // histogram cleared
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-          const uint32_t i = c * kWChunk + j * kTailThreads + threadIdx.x;
-          bb[j] = i < nc ? bm(comp(kk[j], ii[j])) : (uint32_t)kBins;
-          rk[j] = bb[j] <= bstar ? atomicAdd(&lh[bb[j]], 1u) : 0u;
-        }
-        __syncthreads();
-        uint32_t base[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {  // reserve each bucket's range for this claim
-          const uint32_t b = threadIdx.x * PER + j;
-          const uint32_t cnt = lh[b];
-          base[j] = cnt ? ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], cnt) : 0u;
-        }
-        __syncthreads();  // every count read before it is overwritten by the base
-#pragma unroll
-        for (int j = 0; j < PER; ++j) lh[threadIdx.x * PER + j] = base[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-          if (bb[j] <= bstar) {
-            const uint32_t slot = lh[bb[j]] + rk[j];
-            if (slot < a.cap_s) {
-              st_coh(&a.skey[slot], kk[j]);
-              st_coh(&a.sidx[slot], ii[j]);
-            } else {
-              flag_err(ctl, ERR_CAP);
-            }
-          }
-        }
-        __syncthreads();  // the bases are read before the next claim clears them
+        if (R == 32) b2_claim<32>(a, c * chunk, nc, bstar, bm, sm, ctl);
+        else if (R == 16) b2_claim<16>(a, c * chunk, nc, bstar, bm, sm, ctl);
+        else b2_claim<8>(a, c * chunk, nc, bstar, bm, sm, ctl);
       }
       if (report(&ph[PH_B2], mine, nchunks, sm)) {
         stamp(ctl, PH_B2);
