@@ -104,6 +104,8 @@ struct Ctl {
   uint32_t* rec;  // the stream's sticky check record (kErrWords words, not cleared per call)
   uint32_t boff[kBins + 1];   // first output slot of each bucket
   uint32_t gfirst[kBins + 1]; // first bucket of each sort group
+  uint32_t bgrp[kBins];       // sort group of each bucket up to b*
+  uint32_t gbase[kBins + 1];  // first output slot of each sort group
 };
 
 // Internal consistency checks.  A failed check means a defect of the library

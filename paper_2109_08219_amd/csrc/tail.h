@@ -726,12 +726,14 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
 }
 
 // One B2 claim: the survivors [first, first + R x kTailThreads) (below nc)
-// all loaded first, then scattered in batches of 8 per thread: bucket
-// counts and each element's rank in its bucket from an LDS histogram, one
-// global reservation per nonzero bucket up to b*, then the stores.
+// all loaded first, then scattered in batches of 8 per thread into their
+// sort groups (group g = gt[bucket], LDS): counts and each element's rank in
+// its group from an LDS histogram, one global reservation per nonzero group,
+// then the stores.  A group's range ends up holding its buckets' elements in
+// no particular order, which its sort in B3 does not need.
 template <int R>
 __device__ __forceinline__ void b2_claim(const TailArgs& a, uint32_t first, uint32_t nc, uint32_t bstar,
-                                         const BucketMap& bm, TailSmem& sm, Ctl* ctl) {
+                                         const BucketMap& bm, const uint32_t* gt, TailSmem& sm, Ctl* ctl) {
   constexpr int kPer = 8;
   constexpr int PER = kBins / kTailThreads;
   uint32_t* lh = sm.u.st.hist;
@@ -750,16 +752,17 @@ __device__ __forceinline__ void b2_claim(const TailArgs& a, uint32_t first, uint
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const uint32_t i = first + (b0 + j) * kTailThreads + threadIdx.x;
-      bb[j] = i < nc ? bm(comp(kk[b0 + j], ii[b0 + j])) : (uint32_t)kBins;
-      rk[j] = bb[j] <= bstar ? atomicAdd(&lh[bb[j]], 1u) : 0u;
+      const uint32_t b = i < nc ? bm(comp(kk[b0 + j], ii[b0 + j])) : (uint32_t)kBins;
+      bb[j] = b <= bstar ? gt[b] : (uint32_t)kBins;  // the group, or kBins: not scattered
+      rk[j] = bb[j] < (uint32_t)kBins ? atomicAdd(&lh[bb[j]], 1u) : 0u;
     }
     __syncthreads();
     uint32_t base[PER];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {  // reserve each bucket's range for this batch
-      const uint32_t b = threadIdx.x * PER + j;
-      const uint32_t cnt = lh[b];
-      base[j] = cnt ? ld_coh(&ctl->boff[b]) + atomicAdd(&ctl->bcur[b], cnt) : 0u;
+    for (int j = 0; j < PER; ++j) {  // reserve each group's range for this batch
+      const uint32_t g = threadIdx.x * PER + j;
+      const uint32_t cnt = lh[g];
+      base[j] = cnt ? ld_coh(&ctl->gbase[g]) + atomicAdd(&ctl->bcur[g], cnt) : 0u;
     }
     __syncthreads();  // every count read before it is overwritten by the base
 #pragma unroll
@@ -767,7 +770,7 @@ __device__ __forceinline__ void b2_claim(const TailArgs& a, uint32_t first, uint
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-      if (bb[j] <= bstar) {
+      if (bb[j] < (uint32_t)kBins) {
         const uint32_t slot = lh[bb[j]] + rk[j];
         if (slot < a.cap_s) {
           st_coh(&a.skey[slot], kk[b0 + j]);
@@ -1277,9 +1280,16 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         if (b > bstar) break;
         const int64_t wb = lb[b] / kGroup;
         const int64_t wp = b == 0 ? -1 : (int64_t)(lb[b - 1] / kGroup);
-        for (int64_t w = wp + 1; w <= wb; ++w) st_coh(&ctl->gfirst[w], b);
+        st_coh(&ctl->bgrp[b], (uint32_t)wb);
+        for (int64_t w = wp + 1; w <= wb; ++w) {
+          st_coh(&ctl->gfirst[w], b);
+          st_coh(&ctl->gbase[w], lb[b]);
+        }
         if (b == bstar)
-          for (uint32_t w = (uint32_t)wb + 1; w <= nwin; ++w) st_coh(&ctl->gfirst[w], bstar + 1);
+          for (uint32_t w = (uint32_t)wb + 1; w <= nwin; ++w) {
+            st_coh(&ctl->gfirst[w], bstar + 1);
+            st_coh(&ctl->gbase[w], lb[b] + cnt[j]);
+          }
       }
       if (threadIdx.x == 0) {
         st_coh(&ctl->ngroups, nwin);
@@ -1302,13 +1312,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       const uint32_t chunk = R * kTailThreads;
       const uint32_t nchunks = (nc + chunk - 1) / chunk;
       uint32_t mine = 0;
+      uint32_t* gt = sm.u.st.sq.key;  // bucket -> sort group, for buckets up to b*
       for (;;) {
         const uint32_t c = claim(&ph[PH_B2], nchunks, sm);
         if (c >= nchunks) break;
-        ++mine;
-        if (R == 32) b2_claim<32>(a, c * chunk, nc, bstar, bm, sm, ctl);
-        else if (R == 16) b2_claim<16>(a, c * chunk, nc, bstar, bm, sm, ctl);
-        else b2_claim<8>(a, c * chunk, nc, bstar, bm, sm, ctl);
+        if (mine++ == 0) {
+          for (uint32_t b = threadIdx.x; b <= bstar; b += kTailThreads) gt[b] = ld_coh(&ctl->bgrp[b]);
+          __syncthreads();
+        }
+        if (R == 32) b2_claim<32>(a, c * chunk, nc, bstar, bm, gt, sm, ctl);
+        else if (R == 16) b2_claim<16>(a, c * chunk, nc, bstar, bm, gt, sm, ctl);
+        else b2_claim<8>(a, c * chunk, nc, bstar, bm, gt, sm, ctl);
       }
       if (report(&ph[PH_B2], mine, nchunks, sm)) {
         stamp(ctl, PH_B2);
