@@ -142,6 +142,20 @@ def test_survivor_sort_routes(kind):
         check_exact(x, k, dt, vals, idx, f"{kind} k={k} alpha={alpha} beta={beta}")
 
 
+def test_many_survivors_scatter():
+    """Millions of survivors (sorted input, short subranges, small beta): the
+    bucket scatter takes claims of 16 or 32 survivors per thread, and at
+    beta = 8 the qualify phase reads whole delegate lists as vectors."""
+    n = (1 << 23) + 5
+    x = synth.sorted_normal_f32(n, 4242)
+    for k, alpha, beta in [(4096, 10, 1), (2500, 10, 1), (16384, 11, 8), (3000, 9, 4)]:
+        say("many survivors", n, k, alpha, beta)
+        vals, idx, st = drt.topk_select(dev(x), k, alpha=alpha, beta=beta, mode=1, stats=True, check=True)
+        torch.cuda.synchronize()
+        assert beta > 1 or st.candidates >= 1 << 21, (k, alpha, beta, st.candidates)
+        check_exact(x, k, "f32", to_np(vals), to_np(idx), f"sorted n={n} k={k} alpha={alpha} beta={beta}")
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_tail_variants_agree(kind):
     """The cooperative tail kernel and the one-kernel-per-step tail give identical output."""
