@@ -56,6 +56,22 @@ struct TopB {
     c[BETA - 4] = c[BETA - 4] > x3 ? c[BETA - 4] : x3;
     clean();
   }
+  // Eight elements at once (BETA = 8): Batcher's 19-comparator network
+  // sorts them and they are merged like push4's four, all eight entries
+  // against the new ones reversed: 39 compare-exchanges or maxima per eight
+  // elements against push4's 42.
+  __device__ __forceinline__ void push8(uint64_t (&x)[8]) {
+    static_assert(BETA == 8, "push8 needs a list of eight");
+    cx(x[0], x[1]); cx(x[2], x[3]); cx(x[4], x[5]); cx(x[6], x[7]);
+    cx(x[0], x[2]); cx(x[1], x[3]); cx(x[4], x[6]); cx(x[5], x[7]);
+    cx(x[1], x[2]); cx(x[5], x[6]);
+    cx(x[0], x[4]); cx(x[1], x[5]); cx(x[2], x[6]); cx(x[3], x[7]);
+    cx(x[2], x[4]); cx(x[3], x[5]);
+    cx(x[1], x[2]); cx(x[3], x[4]); cx(x[5], x[6]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c[7 - j] = c[7 - j] > x[j] ? c[7 - j] : x[j];
+    clean();
+  }
   // Replace this list by the top-BETA of (this list, the list of a lane in
   // the other M-half of this lane's 2M-block); after the step both lanes hold
   // the same list, so steps M = 1, 2, 4, ... leave every lane of each block
@@ -490,7 +506,17 @@ __device__ __forceinline__ void grouped_batches(const uint32_t* __restrict__ key
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t pu = (uint32_t)p0 + (uint32_t)u * G * 4;
-          if constexpr (BETA >= 4) {
+          if constexpr (BETA == 8) {
+            if (u & 1) continue;  // pairs of loads: u and u + 1
+            const uint32_t pv = pu + G * 4;
+            uint64_t x[8];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              x[c] = comp(enc<DT>(v[u][c]), pu + c);
+              x[4 + c] = comp(enc<DT>(v[u + 1][c]), pv + c);
+            }
+            tb.push8(x);
+          } else if constexpr (BETA >= 4) {
             tb.push4(comp(enc<DT>(v[u][0]), pu), comp(enc<DT>(v[u][1]), pu + 1), comp(enc<DT>(v[u][2]), pu + 2),
                      comp(enc<DT>(v[u][3]), pu + 3));
           } else {
