@@ -1067,8 +1067,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       }
     } else {
       // beta = 4 or 8: each subrange's delegate list is beta / 4 16-byte
-      // vectors of keys and as many of positions, all of the claim's loaded
-      // before any is tested
+      // vectors of keys and as many of positions (the delegate arrays start
+      // 256-byte aligned in the workspace), all of the claim's loaded before
+      // any is tested
       constexpr int NV = BETA / 4;
       for (;;) {
         const uint32_t c = claim(&ph[PH_Q], nchunks, sm);
