@@ -729,8 +729,9 @@ __device__ __forceinline__ void s_claim_vec(const TailArgs& a, uint64_t first, u
 // all loaded first, then scattered in batches of 8 per thread into their
 // sort groups (group g = gt[bucket], LDS): counts and each element's rank in
 // its group from an LDS histogram, one global reservation per nonzero group,
-// then the stores.  A group's range ends up holding its buckets' elements in
-// no particular order, which its sort in B3 does not need.
+// then the stores (ctl->bcur serves as the groups' cursors).  A group's range
+// ends up holding its buckets' elements in no particular order, which its
+// sort in B3 does not need.
 template <int R>
 __device__ __forceinline__ void b2_claim(const TailArgs& a, uint32_t first, uint32_t nc, uint32_t bstar,
                                          const BucketMap& bm, const uint32_t* gt, TailSmem& sm, Ctl* ctl) {
@@ -1313,6 +1314,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
       const uint32_t chunk = R * kTailThreads;
       const uint32_t nchunks = (nc + chunk - 1) / chunk;
       uint32_t mine = 0;
+      static_assert(kBins <= 8 * kTailThreads, "the bucket-to-group table fits the idle Q stage");
       uint32_t* gt = sm.u.st.sq.key;  // bucket -> sort group, for buckets up to b*
       for (;;) {
         const uint32_t c = claim(&ph[PH_B2], nchunks, sm);
