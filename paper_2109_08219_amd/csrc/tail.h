@@ -1123,11 +1123,15 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   {
     const uint32_t nq = ld_coh(&ctl->nq) < ctl->cap_q ? ld_coh(&ctl->nq) : ctl->cap_q;
     const uint64_t total = (uint64_t)nq << a.alpha;
-    // claims of 1..16 steps of kTailThreads x 4 elements: the largest that
-    // still gives every block a claim, so short re-reads spread over the device
+    // claims of 1..16 steps of kTailThreads x 4 elements: the fewest that
+    // cover the re-read in at most 1.25 rounds of claims over the device
+    // (each claim costs a chain of latencies, so one larger claim per block
+    // beats two smaller ones; a few extra claims are taken by the blocks that
+    // finish first), 16 when even those take several rounds
     constexpr uint32_t kStep = kTailThreads * 4;
-    uint32_t steps = kSChunk / kStep;
-    while (steps > 1 && (total + (uint64_t)steps * kStep - 1) / ((uint64_t)steps * kStep) < gridDim.x) steps >>= 1;
+    const uint64_t tsteps = (total + kStep - 1) / kStep;
+    uint32_t steps = 1;
+    while (steps < kSChunk / kStep && (uint64_t)steps * gridDim.x * 5 < tsteps * 4) steps <<= 1;
     const uint32_t chunk = steps * kStep;
     const uint32_t nchunks = (uint32_t)((total + chunk - 1) / chunk);
     const uint64_t lmask = (1ull << a.alpha) - 1;
