@@ -757,9 +757,14 @@ __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t
     __syncthreads();
     const int sh = pass_shift(p);
     const uint32_t dm = (1u << pass_bits(p)) - 1;
-    for (uint32_t i = threadIdx.x; i < E; i += kBT) {
-      const uint64_t x = ld_coh64(&Dg[i]);
-      if ((x & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x >> sh) & dm], 1u);
+    // eight coherent loads in flight per thread before any is counted
+    for (uint32_t i0 = threadIdx.x; i0 < E; i0 += 8 * kBT) {
+      uint64_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = i0 + u * kBT < E ? ld_coh64(&Dg[i0 + u * kBT]) : 0ull;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u * kBT < E && (x[u] & mask) == prefix) atomicAdd(&sm.hist[(uint32_t)(x[u] >> sh) & dm], 1u);
     }
     __syncthreads();
     bb_bucket(sm.hist, r, sm);
@@ -779,13 +784,21 @@ __device__ inline uint32_t b_cut_global(const uint64_t* Dg, uint32_t S, uint32_t
   __syncthreads();
   // a subrange's first delegate is its largest: any of its entries in the
   // class or above puts the first there, so at most above + cls subranges
-  for (uint32_t s = threadIdx.x; s < S; s += kBT) {
-    const uint64_t x = ld_coh64(&Dg[s * BETA]);
-    if ((x & mask) >= prefix) {
-      const uint32_t j = atomicAdd(&sm.nq, 1u);
-      sm.D[j * BETA] = x;
-      if constexpr (BETA == 2) sm.D[j * BETA + 1] = ld_coh64(&Dg[s * BETA + 1]);
+  for (uint32_t s0 = threadIdx.x; s0 < S; s0 += 8 * kBT) {
+    uint64_t x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t s = s0 + u * kBT;
+      x[u] = s < S ? ld_coh64(&Dg[s * BETA]) : 0ull;
+      y[u] = BETA == 2 && s < S ? ld_coh64(&Dg[s * BETA + 1]) : 0ull;
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u * kBT < S && (x[u] & mask) >= prefix) {
+        const uint32_t j = atomicAdd(&sm.nq, 1u);
+        sm.D[j * BETA] = x[u];
+        if constexpr (BETA == 2) sm.D[j * BETA + 1] = y[u];
+      }
   }
   __syncthreads();
   const uint32_t cnt = sm.nq * BETA;
@@ -841,7 +854,14 @@ __device__ inline void b_tile(const BatchDesc& d, uint32_t tile, uint32_t* arriv
   if (threadIdx.x == 0) sm.tail_del = n4 < n ? ld_coh64(&Dg[d.doff + (n4 >> alpha) * BETA + BETA - 1]) : 0;
   uint32_t cnt = S * BETA;
   if (cnt <= kBMaxS) {
-    for (uint32_t i = threadIdx.x; i < cnt; i += kBT) sm.D[i] = ld_coh64(&Dg[d.doff + i]);
+    for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += 8 * kBT) {  // eight loads in flight per thread
+      uint64_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = i0 + u * kBT < cnt ? ld_coh64(&Dg[d.doff + i0 + u * kBT]) : 0ull;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u * kBT < cnt) sm.D[i0 + u * kBT] = x[u];
+    }
     __syncthreads();
   } else {
     cnt = b_cut_global<BETA>(Dg + d.doff, S, d.k, sm);
